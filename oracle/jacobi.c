@@ -1,0 +1,501 @@
+/*
+ * One-sided Jacobi oracle (pointwise and block).  TEST INFRASTRUCTURE ONLY:
+ * it is the plain, slow, obviously correct CPU reference that the GPU
+ * library is checked against.  Only tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load it; the product path never does.
+ *
+ * This one source file is compiled three times, with `real` set to
+ * double (suffix _d), long double (_l) and __float128 (_q).  Inputs and
+ * outputs are always FP64 arrays; the _l and _q builds convert once on
+ * entry and round once on exit, so they serve as high-precision truth for
+ * the accuracy pins.  Build with -ffp-contract=off and without
+ * -ffast-math: every product and sum below is one IEEE operation.
+ *
+ * Problem (Sec. 1, (1.3) and the hyperbolic SVD that follows it): given a
+ * factor G (m x n, column-major, full column rank) and J = diag(j_i),
+ * j_i in {+1,-1}, find V with V^T J V = J such that G V = U Sigma has
+ * orthogonal columns.  Then H = G J G^T has eigenvalues
+ * lambda_i = j_i ||(G V)_i||^2 and eigenvectors (G V)_i / ||(G V)_i||
+ * (Sec. 1: squared column norms of the final factor are the eigenvalues;
+ * Sec. 3.2: the eigenvector matrix comes from normalising the columns of
+ * G V).  J = I is the positive definite (trigonometric) case.
+ *
+ * The method (Sec. 2.1, hyperbolic one-sided Jacobi): repeatedly pick a
+ * pair of columns (g_p, g_q), form the 2x2 Gram A_P = [g_p g_q]^T [g_p g_q],
+ * and transform the pair from the right by the 2x2 matrix that
+ * diagonalises A_P: a trigonometric rotation (2.1) when j_p == j_q, a
+ * hyperbolic one otherwise.  The same 2x2 matrix is applied to the columns
+ * p, q of V.  A sweep visits every pair once in the chosen ordering.
+ */
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+#if defined(ORC_QUAD)
+#include <quadmath.h>
+typedef __float128 real;
+#define R_SQRT(x) sqrtq(x)
+#define R_FABS(x) fabsq(x)
+#define SFX(name) name##_q
+#elif defined(ORC_LONG)
+typedef long double real;
+#define R_SQRT(x) sqrtl(x)
+#define R_FABS(x) fabsl(x)
+#define SFX(name) name##_l
+#else
+typedef double real;
+#define R_SQRT(x) sqrt(x)
+#define R_FABS(x) fabs(x)
+#define SFX(name) name##_d
+#endif
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENONFINITE = -2, ORC_ENOCONV = -3,
+       ORC_ENOMEM = -5 };
+
+int orc_ordering(int n, int kind, int *step_start, int *pairs, int *npairs_out);
+
+static int is_finite_r(real x) { return (x - x) == (x - x); }
+
+/* Gram entries of the column pair (x, y) of length len: x.x, y.y, x.y,
+ * summed left to right (Sec. 2.1, step 1 of the hyperbolic algorithm;
+ * (3.4) for one column per block). */
+static void pair_gram(const real *x, const real *y, int len,
+                      real *axx, real *ayy, real *axy)
+{
+    real sxx = 0, syy = 0, sxy = 0;
+    for (int k = 0; k < len; ++k) {
+        sxx = sxx + x[k] * x[k];
+        syy = syy + y[k] * y[k];
+        sxy = sxy + x[k] * y[k];
+    }
+    *axx = sxx; *ayy = syy; *axy = sxy;
+}
+
+/*
+ * 2x2 transform that diagonalises A_P = [[app, apq], [apq, aqq]]
+ * (Sec. 2.1 step 2).  The paper does not print the formulas; these are the
+ * standard ones, derived as follows.
+ *
+ * Trigonometric, Q = [[c, s], [-s, c]] (the real case of (2.1), sign
+ * convention of (A.1)): the new pair is (c g_p - s g_q, s g_p + c g_q); its
+ * off-diagonal Gram entry is cs(app - aqq) + (c^2 - s^2) apq.  With
+ * t = s/c and zeta = (aqq - app) / (2 apq) it vanishes iff
+ * t^2 + 2 zeta t - 1 = 0; the root of smaller modulus is
+ * t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)), and c = 1/sqrt(1+t^2), s = c t.
+ *
+ * Hyperbolic, Q = [[ch, sh], [sh, ch]] (Sec. 2.1, hyperbolic algorithm):
+ * the new pair is (ch g_p + sh g_q, sh g_p + ch g_q); its off-diagonal
+ * Gram entry is ch sh (app + aqq) + (ch^2 + sh^2) apq.  With t = sh/ch
+ * (= tanh) and zeta = (app + aqq) / (2 apq) it vanishes iff
+ * t^2 + 2 zeta t + 1 = 0; the root of smaller modulus is
+ * t = -sgn(zeta) / (|zeta| + sqrt((|zeta|-1)(|zeta|+1))), and
+ * ch = 1/sqrt((1-t)(1+t)), sh = ch t.  Q^T diag(1,-1) Q = diag(1,-1).
+ * Since A_P is positive semidefinite, app + aqq >= 2|apq|, so |zeta| >= 1 in
+ * exact arithmetic; when rounding gives |zeta| <= 1 (|t| would be 1) the
+ * transform would be singular, and a smaller angle with |tanh| = 0.9 is
+ * used instead (Sec. 3.2).
+ *
+ * sgn(zeta) is +1 for zeta >= 0, including -0.  For |zeta| > 1e150
+ * (zeta^2 would overflow) t is replaced by its limit 1/(2 zeta) (trig) or
+ * -1/(2 zeta) (hyperbolic).  Returns 1 if the hyperbolic clamp was used.
+ */
+static int rotation_params(real app, real aqq, real apq, int same_sign,
+                           real *c_out, real *s_out)
+{
+    real zeta, t, c;
+    int clamped = 0;
+    if (same_sign) {
+        zeta = (aqq - app) / (2 * apq);
+        if (R_FABS(zeta) > (real)1e150) {
+            t = 1 / (2 * zeta);
+        } else {
+            real sg = (zeta >= 0) ? 1 : -1;
+            t = sg / (R_FABS(zeta) + R_SQRT(1 + zeta * zeta));
+        }
+        c = 1 / R_SQRT(1 + t * t);
+    } else {
+        zeta = (app + aqq) / (2 * apq);
+        real sg = (zeta >= 0) ? 1 : -1;
+        real az = R_FABS(zeta);
+        if (az <= 1) {
+            t = -sg * (real)0.9;
+            clamped = 1;
+        } else if (az > (real)1e150) {
+            t = -1 / (2 * zeta);
+        } else {
+            t = -sg / (az + R_SQRT((az - 1) * (az + 1)));
+        }
+        c = 1 / R_SQRT((1 - t) * (1 + t));
+    }
+    *c_out = c;
+    *s_out = c * t;
+    return clamped;
+}
+
+/* Apply the 2x2 transform to the columns x, y (length len):
+ * trig (x, y) <- (c x - s y, s x + c y); hyperbolic (x, y) <- (c x + s y, s x + c y)
+ * (Sec. 2.1 step 3; (A.1)). */
+static void apply_pair(real *x, real *y, int len, real c, real s, int same_sign)
+{
+    for (int k = 0; k < len; ++k) {
+        real xk = x[k], yk = y[k];
+        if (same_sign) {
+            x[k] = c * xk - s * yk;
+            y[k] = s * xk + c * yk;
+        } else {
+            x[k] = c * xk + s * yk;
+            y[k] = s * xk + c * yk;
+        }
+    }
+}
+
+/*
+ * One pivot pair: Gram, threshold, transform.  The pair is rotated only if
+ * |apq| > tol sqrt(app) sqrt(aqq) (a zero column is never rotated).
+ * Returns 1 if rotated, 0 if skipped, ORC_ENONFINITE on a non-finite Gram.
+ */
+static int process_pair(real *X, int ldx, int len, real *W, int ldw, int wlen,
+                        int p, int q, int same_sign, real tol, long long *nclamp)
+{
+    real app, aqq, apq, c, s;
+    real *xp = X + (size_t)p * ldx, *xq = X + (size_t)q * ldx;
+    pair_gram(xp, xq, len, &app, &aqq, &apq);
+    if (!is_finite_r(app) || !is_finite_r(aqq) || !is_finite_r(apq))
+        return ORC_ENONFINITE;
+    if (app == 0 || aqq == 0) return 0;
+    if (!(R_FABS(apq) > tol * R_SQRT(app) * R_SQRT(aqq))) return 0;
+    if (rotation_params(app, aqq, apq, same_sign, &c, &s) && nclamp) ++*nclamp;
+    apply_pair(xp, xq, len, c, s, same_sign);
+    if (W) apply_pair(W + (size_t)p * ldw, W + (size_t)q * ldw, wlen, c, s, same_sign);
+    return 1;
+}
+
+/* Exported for the rotation-parameter pins ((A.3)). */
+int SFX(orc_rotation)(double app, double aqq, double apq, int same_sign,
+                      double *c, double *s)
+{
+    real cr, sr;
+    int cl = rotation_params((real)app, (real)aqq, (real)apq, same_sign, &cr, &sr);
+    *c = (double)cr; *s = (double)sr;
+    return cl;
+}
+
+static void finalize(int m, int n, const real *Gr, const signed char *J,
+                     double *G, int ldg, double *lambda)
+{
+    for (int i = 0; i < n; ++i) {
+        real nrm2 = 0;
+        for (int k = 0; k < m; ++k) nrm2 = nrm2 + Gr[(size_t)i * m + k] * Gr[(size_t)i * m + k];
+        if (lambda) lambda[i] = (double)((J && J[i] < 0) ? -nrm2 : nrm2);
+        for (int k = 0; k < m; ++k) G[(size_t)i * ldg + k] = (double)Gr[(size_t)i * m + k];
+    }
+}
+
+static int check_args(int m, int n, int ldg, const signed char *J, int ldv, const double *V)
+{
+    if (n < 1 || m < n || ldg < m) return ORC_EINVAL;
+    if (V && ldv < n) return ORC_EINVAL;
+    if (J) for (int i = 0; i < n; ++i) if (J[i] != 1 && J[i] != -1) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+/*
+ * Pointwise one-sided Jacobi.  G (m x n, ld ldg) is overwritten by the final
+ * iterate G V.  J: n entries in {+1,-1}, NULL means J = I.  ordering: 0
+ * row-cyclic, 1 modulus, 2 modified modulus.  V (n x n, ld ldv) may be NULL;
+ * if accumulate_v, V holds a prior transform on entry, else V := I.
+ * A sweep is one pass over the ordering; the iteration stops after the first
+ * sweep that rotates no pair (so *sweeps_out counts that sweep too), or
+ * returns ORC_ENOCONV after max_sweeps sweeps, leaving the current iterate.
+ * lambda[i] = j_i ||g_i||^2 of the final iterate.  rot_per_sweep (optional,
+ * max_sweeps entries) receives the rotations of each sweep.
+ */
+int SFX(orc_jevd)(int m, int n, double *G, int ldg, const signed char *J, double tol,
+                  int ordering, int max_sweeps, int accumulate_v,
+                  double *lambda, double *V, int ldv, int *sweeps_out,
+                  long long *rot_per_sweep, long long *nclamp_out)
+{
+    int st = check_args(m, n, ldg, J, ldv, V);
+    if (st) return st;
+    if (max_sweeps < 1) return ORC_EINVAL;
+    int npairs = 0;
+    int nsteps = orc_ordering(n, ordering, NULL, NULL, &npairs);
+    if (nsteps < 0) return ORC_EINVAL;
+    int *step_start = (int *)malloc(sizeof(int) * (size_t)(nsteps + 1));
+    int *pairs = (int *)malloc(sizeof(int) * 2 * (size_t)(npairs > 0 ? npairs : 1));
+    real *Gr = (real *)malloc(sizeof(real) * (size_t)m * n);
+    real *Vr = V ? (real *)malloc(sizeof(real) * (size_t)n * n) : NULL;
+    if (!step_start || !pairs || !Gr || (V && !Vr)) {
+        free(step_start); free(pairs); free(Gr); free(Vr);
+        return ORC_ENOMEM;
+    }
+    orc_ordering(n, ordering, step_start, pairs, NULL);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < m; ++k) Gr[(size_t)i * m + k] = (real)G[(size_t)i * ldg + k];
+    if (Vr)
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k)
+                Vr[(size_t)i * n + k] = accumulate_v ? (real)V[(size_t)i * ldv + k]
+                                                     : (real)(i == k ? 1 : 0);
+    long long nclamp = 0;
+    int sweeps = 0;
+    st = ORC_ENOCONV;
+    while (sweeps < max_sweeps) {
+        long long rot = 0;
+        ++sweeps;
+        for (int sidx = 0; sidx < nsteps && st != ORC_ENONFINITE; ++sidx)
+            for (int e = step_start[sidx]; e < step_start[sidx + 1]; ++e) {
+                int p = pairs[2 * e], q = pairs[2 * e + 1];
+                int same = !J || J[p] == J[q];
+                int r = process_pair(Gr, m, m, Vr, n, n, p, q, same, (real)tol, &nclamp);
+                if (r < 0) { st = r; break; }
+                rot += r;
+            }
+        if (rot_per_sweep) rot_per_sweep[sweeps - 1] = rot;
+        if (st == ORC_ENONFINITE) break;
+        if (rot == 0) { st = ORC_OK; break; }
+    }
+    finalize(m, n, Gr, J, G, ldg, lambda);
+    if (Vr)
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) V[(size_t)i * ldv + k] = (double)Vr[(size_t)i * n + k];
+    if (sweeps_out) *sweeps_out = sweeps;
+    if (nclamp_out) *nclamp_out = nclamp;
+    free(step_start); free(pairs); free(Gr); free(Vr);
+    return st;
+}
+
+/* ------------------------------------------------------------------------
+ * Block one-sided Jacobi (Sec. 2.2-2.3, Alg. 3.4 with unpivoted Cholesky).
+ *
+ * Columns are split into N = 2 ceil(n / (2b)) block columns whose widths
+ * differ by at most one (Sec. 3: uniform partition).  Block pairs (I, J)
+ * follow the modified modulus ordering over the N blocks.  For one pivot
+ * block G_P = [G_I G_J] (m x w):
+ *   1. A_P = G_P^T G_P                                           ((3.4))
+ *   2. skip the pivot if every targeted off-diagonal entry satisfies
+ *      |a_kl| <= tol sqrt(a_kk) sqrt(a_ll)
+ *   3. Cholesky A_P = R^T R, R upper triangular                  (Sec. 2.3)
+ *   4. one-sided Jacobi on the columns of the square factor R, accumulating
+ *      the transforms in V_P (starting from I):
+ *        block-oriented, first step of a sweep: one inner sweep over all
+ *          pairs of the w columns;
+ *        block-oriented, other steps: one inner sweep over the pairs (k, l)
+ *          with k in I and l in J only (annihilate each entry of A_IJ once);
+ *        full block: inner sweeps over all pairs until one rotates nothing
+ *          (or max_inner sweeps).                                (Sec. 2.2)
+ *   5. G_P <- G_P V_P and V(:, P) <- V(:, P) V_P  (one update per pivot,
+ *      Sec. 2.3).
+ * If the Cholesky factorisation breaks down (a non-positive pivot), step 4
+ * runs on the columns of G_P itself instead of R.
+ * Inner orderings: over all w columns the modified modulus ordering (odd
+ * modulus for odd w); over the I x J pairs the bipartite shift: step
+ * s = 0..L-1 (L = max(w_I, w_J)) holds the pairs (k, w_I + (k+s) mod L)
+ * with k < w_I and (k+s) mod L < w_J.
+ * Outer stopping rule: stop after the first block sweep that applies no
+ * inner rotation anywhere.
+ * ---------------------------------------------------------------------- */
+
+/* Inner sweep over a pair list on the columns of X (len rows, ld ldx). */
+static long long inner_sweep(real *X, int ldx, int len, real *VP, int w,
+                             const int *step_start, const int *pairs, int nsteps,
+                             const signed char *JP, real tol, long long *nclamp, int *bad)
+{
+    long long rot = 0;
+    for (int sidx = 0; sidx < nsteps; ++sidx)
+        for (int e = step_start[sidx]; e < step_start[sidx + 1]; ++e) {
+            int p = pairs[2 * e], q = pairs[2 * e + 1];
+            int same = JP[p] == JP[q];
+            int r = process_pair(X, ldx, len, VP, w, w, p, q, same, tol, nclamp);
+            if (r < 0) { *bad = 1; return rot; }
+            rot += r;
+        }
+    return rot;
+}
+
+/* Bipartite shift ordering of the wi x wj cross pairs (see above). */
+static int cross_ordering(int wi, int wj, int *step_start, int *pairs)
+{
+    int L = wi > wj ? wi : wj, np = 0;
+    for (int s = 0; s < L; ++s) {
+        step_start[s] = np;
+        for (int k = 0; k < wi; ++k) {
+            int l = (k + s) % L;
+            if (l < wj) { pairs[2 * np] = k; pairs[2 * np + 1] = wi + l; ++np; }
+        }
+    }
+    step_start[L] = np;
+    return L;
+}
+
+int SFX(orc_block_jevd)(int m, int n, double *G, int ldg, const signed char *J, double tol,
+                        int b, int full_block, int max_sweeps, int max_inner,
+                        int accumulate_v, double *lambda, double *V, int ldv,
+                        int *sweeps_out, long long *rot_per_sweep,
+                        long long *nbreakdown_out)
+{
+    int st = check_args(m, n, ldg, J, ldv, V);
+    if (st) return st;
+    if (b < 1 || max_sweeps < 1 || max_inner < 1) return ORC_EINVAL;
+    int N = 2 * ((n + 2 * b - 1) / (2 * b));
+    if (N > n) return ORC_EINVAL;             /* every block needs a column */
+    int *bstart = (int *)malloc(sizeof(int) * (size_t)(N + 1));
+    int onp = 0;
+    int ons = orc_ordering(N, 2, NULL, NULL, &onp);
+    int *ostart = (int *)malloc(sizeof(int) * (size_t)(ons + 1));
+    int *opairs = (int *)malloc(sizeof(int) * 2 * (size_t)onp);
+    int wmax = 2 * (n / N + 1);
+    int maxp = wmax * wmax;                   /* bound on inner pair counts */
+    int *istart = (int *)malloc(sizeof(int) * (size_t)(wmax + 1));
+    int *ipairs = (int *)malloc(sizeof(int) * 2 * (size_t)maxp);
+    real *Gr = (real *)malloc(sizeof(real) * (size_t)m * n);
+    real *Vr = V ? (real *)malloc(sizeof(real) * (size_t)n * n) : NULL;
+    real *GP = (real *)malloc(sizeof(real) * (size_t)m * wmax);
+    real *VB = (real *)malloc(sizeof(real) * (size_t)n * wmax);
+    real *AP = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
+    real *R = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
+    real *VP = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
+    signed char *JP = (signed char *)malloc((size_t)wmax);
+    int *colp = (int *)malloc(sizeof(int) * (size_t)wmax);
+    if (!bstart || !ostart || !opairs || !istart || !ipairs || !Gr || (V && !Vr) ||
+        !GP || !VB || !AP || !R || !VP || !JP || !colp) {
+        st = ORC_ENOMEM;
+        goto out;
+    }
+    orc_ordering(N, 2, ostart, opairs, NULL);
+    bstart[0] = 0;
+    for (int k = 0; k < N; ++k) bstart[k + 1] = bstart[k] + n / N + (k < n % N ? 1 : 0);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < m; ++k) Gr[(size_t)i * m + k] = (real)G[(size_t)i * ldg + k];
+    if (Vr)
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k)
+                Vr[(size_t)i * n + k] = accumulate_v ? (real)V[(size_t)i * ldv + k]
+                                                     : (real)(i == k ? 1 : 0);
+    long long nclamp = 0, nbreak = 0;
+    int sweeps = 0;
+    st = ORC_ENOCONV;
+    while (sweeps < max_sweeps) {
+        long long rot = 0;
+        int bad = 0;
+        ++sweeps;
+        for (int sidx = 0; sidx < ons && !bad; ++sidx) {
+            for (int e = ostart[sidx]; e < ostart[sidx + 1] && !bad; ++e) {
+                int I = opairs[2 * e], Jb = opairs[2 * e + 1];
+                int wi = bstart[I + 1] - bstart[I], wj = bstart[Jb + 1] - bstart[Jb];
+                int w = wi + wj;
+                for (int k = 0; k < wi; ++k) colp[k] = bstart[I] + k;
+                for (int k = 0; k < wj; ++k) colp[wi + k] = bstart[Jb] + k;
+                for (int k = 0; k < w; ++k) {
+                    JP[k] = (J && J[colp[k]] < 0) ? -1 : 1;
+                    memcpy(GP + (size_t)k * m, Gr + (size_t)colp[k] * m, sizeof(real) * (size_t)m);
+                }
+                /* 1. pivot Gram */
+                for (int k = 0; k < w; ++k)
+                    for (int l = 0; l < w; ++l) {
+                        real acc = 0;
+                        for (int r = 0; r < m; ++r)
+                            acc = acc + GP[(size_t)k * m + r] * GP[(size_t)l * m + r];
+                        AP[(size_t)l * w + k] = acc;
+                    }
+                /* 2. skip test on the targeted entries */
+                int all_pairs = full_block || sidx == 0;
+                int need = 0;
+                for (int k = 0; k < w && !bad; ++k)
+                    for (int l = k + 1; l < w; ++l) {
+                        if (!all_pairs && !(k < wi && l >= wi)) continue;
+                        real akk = AP[(size_t)k * w + k], all = AP[(size_t)l * w + l];
+                        real akl = AP[(size_t)l * w + k];
+                        if (!is_finite_r(akk) || !is_finite_r(all) || !is_finite_r(akl)) {
+                            bad = 1; break;
+                        }
+                        if (akk != 0 && all != 0 &&
+                            R_FABS(akl) > (real)tol * R_SQRT(akk) * R_SQRT(all))
+                            need = 1;
+                    }
+                if (bad || !need) continue;
+                /* 3. Cholesky A_P = R^T R (upper R, column-major w x w) */
+                int broke = 0;
+                for (int j = 0; j < w && !broke; ++j) {
+                    for (int i = 0; i <= j; ++i) {
+                        real sum = AP[(size_t)j * w + i];
+                        for (int k = 0; k < i; ++k)
+                            sum = sum - R[(size_t)i * w + k] * R[(size_t)j * w + k];
+                        if (i == j) {
+                            if (!(sum > 0)) { broke = 1; break; }
+                            R[(size_t)j * w + j] = R_SQRT(sum);
+                        } else {
+                            R[(size_t)j * w + i] = sum / R[(size_t)i * w + i];
+                        }
+                    }
+                    for (int i = j + 1; i < w; ++i) R[(size_t)j * w + i] = 0;
+                }
+                if (broke) ++nbreak;
+                /* 4. inner one-sided Jacobi on R (or on G_P after a breakdown) */
+                real *X = broke ? GP : R;
+                int ldx = broke ? m : w, len = broke ? m : w;
+                for (int k = 0; k < w; ++k)
+                    for (int l = 0; l < w; ++l) VP[(size_t)k * w + l] = (real)(k == l ? 1 : 0);
+                long long prot = 0;
+                int isteps, inp = 0;
+                if (all_pairs) {
+                    isteps = orc_ordering(w, 2, istart, ipairs, &inp);
+                } else {
+                    isteps = cross_ordering(wi, wj, istart, ipairs);
+                }
+                int inner = full_block ? max_inner : 1;
+                for (int it = 0; it < inner; ++it) {
+                    long long r = inner_sweep(X, ldx, len, VP, w, istart, ipairs, isteps,
+                                              JP, (real)tol, &nclamp, &bad);
+                    prot += r;
+                    if (bad || r == 0) break;
+                }
+                if (bad) break;
+                rot += prot;
+                /* 5. update G_P <- G_P V_P, V(:,P) <- V(:,P) V_P.  After a
+                 * breakdown G_P was transformed in place and is copied back. */
+                if (prot > 0) {
+                    if (broke) {
+                        for (int c = 0; c < w; ++c)
+                            memcpy(Gr + (size_t)colp[c] * m, GP + (size_t)c * m,
+                                   sizeof(real) * (size_t)m);
+                    } else {
+                        for (int c = 0; c < w; ++c)
+                            for (int r = 0; r < m; ++r) {
+                                real acc = 0;
+                                for (int k = 0; k < w; ++k)
+                                    acc = acc + GP[(size_t)k * m + r] * VP[(size_t)c * w + k];
+                                Gr[(size_t)colp[c] * m + r] = acc;
+                            }
+                    }
+                    if (Vr) {
+                        for (int k = 0; k < w; ++k)
+                            memcpy(VB + (size_t)k * n, Vr + (size_t)colp[k] * n,
+                                   sizeof(real) * (size_t)n);
+                        for (int c = 0; c < w; ++c)
+                            for (int r = 0; r < n; ++r) {
+                                real acc = 0;
+                                for (int k = 0; k < w; ++k)
+                                    acc = acc + VB[(size_t)k * n + r] * VP[(size_t)c * w + k];
+                                Vr[(size_t)colp[c] * n + r] = acc;
+                            }
+                    }
+                }
+            }
+        }
+        if (rot_per_sweep) rot_per_sweep[sweeps - 1] = rot;
+        if (bad) { st = ORC_ENONFINITE; break; }
+        if (rot == 0) { st = ORC_OK; break; }
+    }
+    finalize(m, n, Gr, J, G, ldg, lambda);
+    if (Vr)
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) V[(size_t)i * ldv + k] = (double)Vr[(size_t)i * n + k];
+    if (sweeps_out) *sweeps_out = sweeps;
+    if (nbreakdown_out) *nbreakdown_out = nbreak;
+out:
+    free(bstart); free(ostart); free(opairs); free(istart); free(ipairs);
+    free(Gr); free(Vr); free(GP); free(VB); free(AP); free(R); free(VP); free(JP);
+    free(colp);
+    return st;
+}

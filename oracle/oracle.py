@@ -1,0 +1,160 @@
+"""ctypes front end of the one-sided Jacobi oracle (plain C, liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: tests, the smoke check and the benchmark's CPU
+baseline leg may call this module; the product path (the HIP library and
+its Python binding) never imports it, and this module imports nothing of
+the product.
+
+Every function takes and returns numpy FP64 arrays.  ``prec`` selects the
+internal arithmetic of the C code: 'd' (double), 'l' (x87 long double,
+64-bit mantissa) or 'q' (__float128); inputs are converted once on entry and
+results rounded once to double on exit, so 'q' runs serve as truth for the
+accuracy pins.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# ORACLE_LIB lets the mutation tests point this front end at a copy of the
+# oracle with a deliberately planted mistake (built in a temporary folder).
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
+
+ROWCYCLIC, MODULUS, MODMODULUS = 0, 1, 2
+STATUS = {0: "ok", -1: "einval", -2: "enonfinite", -3: "enoconv", -5: "enomem"}
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_llp = ctypes.POINTER(ctypes.c_longlong)
+_cp = ctypes.c_void_p
+
+
+def lib():
+    """Load liboracle.so (building it first if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b  # noqa: F401  (package-relative import)
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.orc_ordering.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _ip, _ip]
+        L.orc_ordering.restype = ctypes.c_int
+        for s in "dlq":
+            f = getattr(L, "orc_jevd_" + s)
+            f.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _cp,
+                          ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          _dp, _dp, ctypes.c_int, _ip, _llp, _llp]
+            f.restype = ctypes.c_int
+            f = getattr(L, "orc_block_jevd_" + s)
+            f.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _cp,
+                          ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _ip,
+                          _llp, _llp]
+            f.restype = ctypes.c_int
+            f = getattr(L, "orc_rotation_" + s)
+            f.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                          ctypes.c_int, _dp, _dp]
+            f.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def ordering(n, kind):
+    """List of steps; each step is a list of 0-based pairs (i, j), i < j."""
+    L = lib()
+    npairs = ctypes.c_int(0)
+    nsteps = L.orc_ordering(n, kind, None, None, ctypes.byref(npairs))
+    if nsteps < 0:
+        raise ValueError("bad ordering arguments")
+    starts = np.zeros(nsteps + 1, dtype=np.int32)
+    pairs = np.zeros(2 * max(npairs.value, 1), dtype=np.int32)
+    L.orc_ordering(n, kind, _ptr(starts, _ip), _ptr(pairs, _ip), None)
+    return [[(int(pairs[2 * e]), int(pairs[2 * e + 1])) for e in range(starts[s], starts[s + 1])]
+            for s in range(nsteps)]
+
+
+class Result:
+    """Outputs of one oracle solve."""
+
+    def __init__(self, status, G, lam, V, sweeps, rot, extra):
+        self.status = status
+        self.G = G            # final iterate G V (m x n)
+        self.lam = lam        # j_i ||g_i||^2 of the final iterate
+        self.V = V            # accumulated transform (n x n) or None
+        self.sweeps = sweeps  # sweeps executed, including the last one without rotations
+        self.rot = rot        # rotations applied in each sweep
+        self.extra = extra    # clamps (pointwise) or Cholesky breakdowns (block)
+
+    @property
+    def U(self):
+        """Eigenvectors: the columns of G V normalised (zero columns stay zero)."""
+        nrm = np.sqrt(np.sum(self.G * self.G, axis=0))
+        safe = np.where(nrm > 0, nrm, 1.0)
+        return self.G / safe
+
+
+def _prep(G, J, want_v, V0):
+    G = np.array(G, dtype=np.float64, order="F", copy=True)
+    m, n = G.shape
+    Jb = None
+    if J is not None:
+        Jb = np.ascontiguousarray(np.asarray(J).astype(np.int8))
+        if Jb.shape != (n,):
+            raise ValueError("J must have n entries")
+    V = None
+    if want_v or V0 is not None:
+        V = np.array(V0 if V0 is not None else np.zeros((n, n)), dtype=np.float64,
+                     order="F", copy=True)
+    return G, m, n, Jb, V
+
+
+def jevd(G, J=None, tol=None, ordering_kind=MODMODULUS, max_sweeps=50, want_v=True,
+         V0=None, prec="d"):
+    """Pointwise one-sided Jacobi; see oracle/jacobi.c.  tol=None means n*DBL_EPSILON."""
+    G, m, n, Jb, V = _prep(G, J, want_v, V0)
+    if tol is None:
+        tol = n * np.finfo(np.float64).eps
+    lam = np.zeros(n)
+    sweeps = ctypes.c_int(0)
+    rot = np.zeros(max(max_sweeps, 1), dtype=np.int64)
+    ncl = ctypes.c_longlong(0)
+    f = getattr(lib(), "orc_jevd_" + prec)
+    st = f(m, n, _ptr(G), m, None if Jb is None else Jb.ctypes.data_as(_cp), float(tol),
+           ordering_kind, max_sweeps, 1 if V0 is not None else 0, _ptr(lam),
+           None if V is None else _ptr(V), n, ctypes.byref(sweeps), _ptr(rot, _llp),
+           ctypes.byref(ncl))
+    return Result(st, G, lam, V, sweeps.value, rot[:sweeps.value].copy(), ncl.value)
+
+
+def block_jevd(G, J=None, tol=None, b=8, full_block=False, max_sweeps=50, max_inner=30,
+               want_v=True, V0=None, prec="d"):
+    """Block one-sided Jacobi (unpivoted Cholesky); see oracle/jacobi.c."""
+    G, m, n, Jb, V = _prep(G, J, want_v, V0)
+    if tol is None:
+        tol = n * np.finfo(np.float64).eps
+    lam = np.zeros(n)
+    sweeps = ctypes.c_int(0)
+    rot = np.zeros(max(max_sweeps, 1), dtype=np.int64)
+    nbr = ctypes.c_longlong(0)
+    f = getattr(lib(), "orc_block_jevd_" + prec)
+    st = f(m, n, _ptr(G), m, None if Jb is None else Jb.ctypes.data_as(_cp), float(tol),
+           b, 1 if full_block else 0, max_sweeps, max_inner, 1 if V0 is not None else 0,
+           _ptr(lam), None if V is None else _ptr(V), n, ctypes.byref(sweeps),
+           _ptr(rot, _llp), ctypes.byref(nbr))
+    return Result(st, G, lam, V, sweeps.value, rot[:sweeps.value].copy(), nbr.value)
+
+
+def rotation(app, aqq, apq, same_sign, prec="d"):
+    """(c, s, clamped) of the 2x2 transform for the Gram (app, aqq, apq)."""
+    c = ctypes.c_double(0)
+    s = ctypes.c_double(0)
+    f = getattr(lib(), "orc_rotation_" + prec)
+    cl = f(float(app), float(aqq), float(apq), 1 if same_sign else 0, ctypes.byref(c),
+           ctypes.byref(s))
+    return c.value, s.value, bool(cl)

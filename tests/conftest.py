@@ -1,0 +1,23 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
+    config.addinivalue_line("markers", "slow: longer CPU test (still part of the default CPU suite)")
+
+
+@pytest.fixture(scope="session")
+def orc():
+    """The oracle front end (built on first use)."""
+    from oracle import oracle as O
+    if not os.path.exists(O.LIB_PATH):
+        from oracle import build as B
+        B.build()
+    return O
