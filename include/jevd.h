@@ -1,0 +1,152 @@
+/*
+ * jevd.h -- one-sided Jacobi eigensolver for AMD MI355X (gfx950): C ABI.
+ *
+ * Problem (Sec. 1, (1.3) and the hyperbolic SVD defined right after it):
+ * H = G J G^T is given by a factor G (m x n, m >= n, full column rank) and a
+ * signature J = diag(j_1..j_n), j_i in {+1, -1}.  The library finds V with
+ * V^T J V = J such that the columns of G V are mutually orthogonal; then the
+ * eigenvalues of H are lambda_i = j_i ||(G V)_i||^2 (Sec. 1: squared column
+ * norms of the final factor) and its eigenvectors are the normalised
+ * columns u_i = (G V)_i / ||(G V)_i|| (Sec. 3.2).  J = I is the positive
+ * definite, purely trigonometric case H = G G^T.
+ *
+ * The method is the one-sided Jacobi sweep (Sec. 2.1): pivot pairs of
+ * columns (pointwise) or of block columns (Sec. 2.2-2.3, block-oriented or
+ * full block, with the Gram of the pivot block factored by Cholesky and the
+ * accumulated transform applied once per pivot) are orthogonalised by
+ * trigonometric rotations when their signs in J agree and by hyperbolic
+ * ones otherwise, in the row-cyclic, modulus or modified modulus ordering
+ * (Sec. 2.4, Alg. 3.1).  A pair is rotated only when
+ * |a_pq| > tol * sqrt(a_pp) * sqrt(a_qq) for its Gram entries; the iteration
+ * stops after the first sweep that rotates nothing.
+ *
+ * Conventions for every entry point:
+ *   - matrices are column-major FP64; element (r, c) of X is X[r + c * ldx];
+ *   - G, lambda, U and V are DEVICE pointers (memory of the device that is
+ *     current when the handle is created); J is a HOST pointer;
+ *   - the caller owns every buffer; a handle owns only its workspace;
+ *   - all work is ordered on the handle's stream; the solver synchronises
+ *     that stream once per sweep (to read the rotation count) and before
+ *     returning, so outputs are ready when the call returns;
+ *   - no C++ exception crosses the ABI; every function returns a status.
+ */
+#ifndef JEVD_H
+#define JEVD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jevd_handle_s *jevd_handle_t;
+
+/* Status codes. */
+enum {
+    JEVD_OK = 0,
+    JEVD_EINVAL = -1,      /* bad argument; detected before any device work */
+    JEVD_ENONFINITE = -2,  /* a NaN or Inf appeared in a Gram entry */
+    JEVD_ENOCONV = -3,     /* max_sweeps reached; outputs hold the current iterate */
+    JEVD_EHIP = -4,        /* a HIP runtime call failed (no device, launch error, ...) */
+    JEVD_ENOMEM = -5       /* device or pinned host allocation failed */
+};
+
+/* Pivot orderings (Sec. 2.4, Fig. 2-3, Alg. 3.1). */
+enum {
+    JEVD_ORD_ROWCYCLIC = 0,   /* (1,2),(1,3),...,(n-1,n): one pair at a time */
+    JEVD_ORD_MODULUS = 1,     /* step k: all pairs with i + j == k (mod n) */
+    JEVD_ORD_MODMODULUS = 2   /* modulus plus the pair of the two idle indices on even steps (default) */
+};
+
+/* Variants (Sec. 2.1-2.2). */
+enum {
+    JEVD_VAR_POINTWISE = 0,       /* 2x2 pivots on single columns */
+    JEVD_VAR_BLOCK_ORIENTED = 1,  /* block pivots; annihilate each entry of A_IJ once per step */
+    JEVD_VAR_FULL_BLOCK = 2,      /* block pivots; diagonalise every pivot block */
+    JEVD_VAR_AUTO = 3             /* pointwise for small n, block-oriented otherwise */
+};
+
+typedef struct {
+    int ordering;      /* JEVD_ORD_*; default JEVD_ORD_MODMODULUS.  Block variants
+                          always order block pairs by the modified modulus ordering. */
+    int variant;       /* JEVD_VAR_*; default JEVD_VAR_AUTO */
+    int block;         /* block width b of the block variants (16, 32 or 64); 0: choose */
+    int max_sweeps;    /* sweep limit, default 50 (>= 1) */
+    int max_inner;     /* full block: inner sweep limit per pivot, default 30 */
+    int accumulate_v;  /* 0: V := I before the first sweep; 1: V holds a prior
+                          transform on entry (resume from an earlier iterate) */
+} jevd_opts;
+
+/* Per-call diagnostics of the last jacobi_evd on a handle. */
+#define JEVD_INFO_MAX_SWEEPS 64
+typedef struct {
+    int sweeps;                                    /* same as the *sweeps output */
+    int variant;                                   /* variant actually run */
+    int block;                                     /* block width used (0: pointwise) */
+    int ordering;                                  /* ordering actually run */
+    long long rotations[JEVD_INFO_MAX_SWEEPS];     /* rotations applied per sweep */
+    long long clamps;                              /* hyperbolic transforms clamped to |tanh| = 0.9 */
+    long long breakdowns;                          /* block pivots whose Cholesky broke down */
+} jevd_info;
+
+/* Fills *o with the defaults listed above.  Never fails for a non-NULL o. */
+int jevd_default_opts(jevd_opts *o);
+
+/* Creates a handle bound to the current device and to `stream` (a
+ * hipStream_t; NULL means the default stream).  *h receives the handle.
+ * Returns JEVD_EINVAL for h == NULL, JEVD_EHIP if no device is usable. */
+int jevd_create(jevd_handle_t *h, void *stream);
+
+/* Frees the handle's workspace.  NULL is accepted. */
+int jevd_destroy(jevd_handle_t h);
+
+/*
+ * jacobi_evd: one-sided Jacobi eigensolver, H = G J G^T.
+ *   m, n     G is m x n with m >= n >= 1; ldg >= m.
+ *   G        device, in/out.  On return it holds the final iterate G V
+ *            (orthogonal columns, U Sigma).  Overwritten in place (Sec. 3.2).
+ *   J        host, n entries each +1 or -1; NULL means J = I.
+ *   tol      rotation threshold; <= 0 means n * DBL_EPSILON.
+ *   opts     NULL means jevd_default_opts.
+ *   lambda   device, n outputs lambda_i = j_i ||g_i||^2 of the final
+ *            iterate, in column order (not sorted); may be NULL.
+ *   U, ldu   device, m x n outputs u_i = g_i / ||g_i|| (zero column -> 0);
+ *            U may equal G (then G is normalised in place); may be NULL.
+ *   V, ldv   device, n x n, the accumulated J-orthogonal transform
+ *            (G_out = G_in V); in/out when opts->accumulate_v; may be NULL
+ *            (then V is not formed, which saves its traffic).
+ *   sweeps   host, receives the sweeps executed, including the final sweep
+ *            that rotates nothing; may be NULL.
+ * Returns JEVD_OK, JEVD_EINVAL (before any device work: m < n, n < 1,
+ * leading dimension too small, J entry not +-1, bad option), JEVD_ENONFINITE,
+ * JEVD_ENOCONV (after max_sweeps sweeps; G, lambda, U and V hold the current
+ * iterate, so a later call with accumulate_v = 1 resumes), JEVD_EHIP or
+ * JEVD_ENOMEM.  Buffers must not overlap except U == G.
+ */
+int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed char *J,
+               double tol, const jevd_opts *opts, double *lambda, double *U, int ldu,
+               double *V, int ldv, int *sweeps);
+
+/* Host-only argument check that jacobi_evd runs before any device work
+ * (same rules; G, lambda and the handle are not examined).  Returns JEVD_OK
+ * or JEVD_EINVAL.  No device work. */
+int jevd_validate(int m, int n, int ldg, const signed char *J, double tol, const jevd_opts *opts,
+                  const double *U, int ldu, const double *V, int ldv);
+
+/* Diagnostics of the last jacobi_evd call on h. */
+int jevd_get_info(jevd_handle_t h, jevd_info *info);
+
+/* Static text for a status code. */
+const char *jevd_strerror(int status);
+
+/*
+ * Host-only helper: the pivot ordering the solver runs (Sec. 2.4, Alg. 3.1),
+ * as 0-based pairs (i < j) grouped in steps.  step_start (nsteps + 1 ints)
+ * and pairs (2 ints per pair) may be NULL to query sizes; *nsteps and
+ * *npairs receive the counts.  Pairs of a step are disjoint.  No device work.
+ */
+int jevd_ordering(int n, int ordering, int *step_start, int *pairs, int *nsteps, int *npairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JEVD_H */

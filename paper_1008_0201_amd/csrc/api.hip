@@ -1,0 +1,331 @@
+// C ABI of the one-sided Jacobi solver (include/jevd.h): argument checks,
+// workspace, the sweep loop and the dispatch to the pointwise and block
+// kernels.
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/jevd.h"
+#include "block.h"
+#include "jevd_internal.h"
+#include "ordering.h"
+
+using namespace jevd;
+
+struct jevd_handle_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    signed char *dJ = nullptr;
+    size_t capJ = 0;
+    SweepCounters *dctr = nullptr;  // one slot per sweep
+    SweepCounters *hctr = nullptr;  // pinned mirror
+    int capCtr = 0;
+    int *dsweeps = nullptr;
+    int *hsweeps = nullptr;  // pinned
+
+    // cached ordering table
+    int tabN = -1, tabOrd = -1;
+    std::vector<int> hstep;
+    int maxPairsPerStep = 0;
+    int2 *dpairs = nullptr;
+    size_t capPairs = 0;
+    int *dstep = nullptr;
+    size_t capStep = 0;
+
+    BlockWorkspace blk;
+    jevd_info info;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) {                         \
+            (void)hipGetLastError();                    \
+            return (_e == hipErrorOutOfMemory) ? JEVD_ENOMEM : JEVD_EHIP; \
+        }                                               \
+    } while (0)
+
+template <class T>
+int grow_device(T **p, size_t *cap, size_t need)
+{
+    if (*cap >= need && *p) return JEVD_OK;
+    if (*p) HIP_TRY(hipFree(*p));
+    *p = nullptr;
+    *cap = 0;
+    HIP_TRY(hipMalloc((void **)p, need * sizeof(T)));
+    *cap = need;
+    return JEVD_OK;
+}
+
+int ensure_counters(jevd_handle_t h, int nslots)
+{
+    if (h->capCtr >= nslots && h->dctr) return JEVD_OK;
+    if (h->dctr) HIP_TRY(hipFree(h->dctr));
+    if (h->hctr) HIP_TRY(hipHostFree(h->hctr));
+    h->dctr = nullptr;
+    h->hctr = nullptr;
+    h->capCtr = 0;
+    HIP_TRY(hipMalloc((void **)&h->dctr, sizeof(SweepCounters) * nslots));
+    HIP_TRY(hipHostMalloc((void **)&h->hctr, sizeof(SweepCounters) * nslots, hipHostMallocDefault));
+    h->capCtr = nslots;
+    return JEVD_OK;
+}
+
+int ensure_ordering(jevd_handle_t h, int n, int ord)
+{
+    if (h->tabN == n && h->tabOrd == ord) return JEVD_OK;
+    std::vector<int> st, pr;
+    if (build_ordering(n, ord, st, pr) < 0) return JEVD_EINVAL;
+    int st_ok = grow_device(&h->dpairs, &h->capPairs, pr.size() / 2 + 1);
+    if (st_ok) return st_ok;
+    st_ok = grow_device(&h->dstep, &h->capStep, st.size());
+    if (st_ok) return st_ok;
+    if (!pr.empty())
+        HIP_TRY(hipMemcpyAsync(h->dpairs, pr.data(), pr.size() * sizeof(int), hipMemcpyHostToDevice,
+                               h->stream));
+    HIP_TRY(hipMemcpyAsync(h->dstep, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));  // host vectors go out of scope
+    h->hstep = st;
+    h->maxPairsPerStep = 0;
+    for (size_t k = 0; k + 1 < st.size(); ++k)
+        if (st[k + 1] - st[k] > h->maxPairsPerStep) h->maxPairsPerStep = st[k + 1] - st[k];
+    h->tabN = n;
+    h->tabOrd = ord;
+    return JEVD_OK;
+}
+
+void fill_defaults(jevd_opts *o)
+{
+    o->ordering = JEVD_ORD_MODMODULUS;
+    o->variant = JEVD_VAR_AUTO;
+    o->block = 0;
+    o->max_sweeps = 50;
+    o->max_inner = 30;
+    o->accumulate_v = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jevd_default_opts(jevd_opts *o)
+{
+    if (!o) return JEVD_EINVAL;
+    fill_defaults(o);
+    return JEVD_OK;
+}
+
+const char *jevd_strerror(int status)
+{
+    switch (status) {
+    case JEVD_OK: return "success";
+    case JEVD_EINVAL: return "invalid argument";
+    case JEVD_ENONFINITE: return "non-finite value (NaN or Inf) in a Gram entry";
+    case JEVD_ENOCONV: return "no convergence within max_sweeps sweeps";
+    case JEVD_EHIP: return "HIP runtime error";
+    case JEVD_ENOMEM: return "out of memory";
+    default: return "unknown status";
+    }
+}
+
+int jevd_ordering(int n, int ordering, int *step_start, int *pairs, int *nsteps, int *npairs)
+{
+    std::vector<int> st, pr;
+    const int ns = build_ordering(n, ordering, st, pr);
+    if (ns < 0) return JEVD_EINVAL;
+    if (nsteps) *nsteps = ns;
+    if (npairs) *npairs = (int)(pr.size() / 2);
+    if (step_start) std::memcpy(step_start, st.data(), st.size() * sizeof(int));
+    if (pairs && !pr.empty()) std::memcpy(pairs, pr.data(), pr.size() * sizeof(int));
+    return JEVD_OK;
+}
+
+// Host-only argument check used by jacobi_evd before any device work.
+int jevd_validate(int m, int n, int ldg, const signed char *J, double tol, const jevd_opts *opts,
+                  const double *U, int ldu, const double *V, int ldv)
+{
+    if (n < 1 || m < n || ldg < m) return JEVD_EINVAL;
+    if (U && ldu < m) return JEVD_EINVAL;
+    if (V && ldv < n) return JEVD_EINVAL;
+    if (std::isnan(tol) || std::isinf(tol)) return JEVD_EINVAL;
+    if (J)
+        for (int i = 0; i < n; ++i)
+            if (J[i] != 1 && J[i] != -1) return JEVD_EINVAL;
+    if (opts) {
+        if (opts->ordering < JEVD_ORD_ROWCYCLIC || opts->ordering > JEVD_ORD_MODMODULUS) return JEVD_EINVAL;
+        if (opts->variant < JEVD_VAR_POINTWISE || opts->variant > JEVD_VAR_AUTO) return JEVD_EINVAL;
+        if (opts->max_sweeps < 1 || opts->max_sweeps > 100000) return JEVD_EINVAL;
+        if (opts->max_inner < 1) return JEVD_EINVAL;
+        if (opts->accumulate_v != 0 && opts->accumulate_v != 1) return JEVD_EINVAL;
+        if (opts->accumulate_v && !V) return JEVD_EINVAL;
+        if (opts->block != 0 && !block_width_supported(opts->block)) return JEVD_EINVAL;
+        if (opts->variant == JEVD_VAR_BLOCK_ORIENTED || opts->variant == JEVD_VAR_FULL_BLOCK) {
+            const int b = opts->block ? opts->block : choose_block_width(m, n);
+            if (!block_shape_supported(m, n, b)) return JEVD_EINVAL;
+        }
+    }
+    return JEVD_OK;
+}
+
+int jevd_create(jevd_handle_t *h, void *stream)
+{
+    if (!h) return JEVD_EINVAL;
+    *h = nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return JEVD_EHIP;
+    }
+    jevd_handle_s *p = new (std::nothrow) jevd_handle_s();
+    if (!p) return JEVD_ENOMEM;
+    p->device = dev;
+    p->stream = (hipStream_t)stream;
+    std::memset(&p->info, 0, sizeof(p->info));
+    if (hipHostMalloc((void **)&p->hsweeps, sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void **)&p->dsweeps, sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        jevd_destroy(p);
+        return JEVD_ENOMEM;
+    }
+    *h = p;
+    return JEVD_OK;
+}
+
+int jevd_destroy(jevd_handle_t h)
+{
+    if (!h) return JEVD_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    if (h->dJ) (void)hipFree(h->dJ);
+    if (h->dctr) (void)hipFree(h->dctr);
+    if (h->hctr) (void)hipHostFree(h->hctr);
+    if (h->dsweeps) (void)hipFree(h->dsweeps);
+    if (h->hsweeps) (void)hipHostFree(h->hsweeps);
+    if (h->dpairs) (void)hipFree(h->dpairs);
+    if (h->dstep) (void)hipFree(h->dstep);
+    block_workspace_free(&h->blk);
+    delete h;
+    return JEVD_OK;
+}
+
+int jevd_get_info(jevd_handle_t h, jevd_info *info)
+{
+    if (!h || !info) return JEVD_EINVAL;
+    *info = h->info;
+    return JEVD_OK;
+}
+
+static int run_pointwise(jevd_handle_t h, int m, int n, double *G, int ldg, const signed char *dJ,
+                         double tol, const jevd_opts &o, double *V, int ldv, int *sweeps_done)
+{
+    int st = ensure_ordering(h, n, o.ordering);
+    if (st) return st;
+    const int nsteps = (int)h->hstep.size() - 1;
+    int lg = 0, lv = 0;
+    const bool small = small_solve_lds_bytes(m, n, V != nullptr, &lg, &lv) > 0 && lg &&
+                       (V == nullptr || lv) && (o.ordering == JEVD_ORD_ROWCYCLIC || n <= 128);
+    if (o.ordering == JEVD_ORD_ROWCYCLIC || small) {
+        // whole solve in one workgroup (all sweeps inside the kernel)
+        HIP_TRY(hipMemsetAsync(h->dctr, 0, sizeof(SweepCounters) * o.max_sweeps, h->stream));
+        SmallSolveArgs a{G, m, n, (long)ldg, V, (long)ldv, dJ, tol, h->dpairs, h->dstep, nsteps,
+                         h->maxPairsPerStep, o.max_sweeps, h->dctr, h->dsweeps};
+        HIP_TRY(launch_small_solve(a, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->hsweeps, h->dsweeps, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->hctr, h->dctr, sizeof(SweepCounters) * o.max_sweeps,
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        const int sw = *h->hsweeps;
+        *sweeps_done = sw;
+        for (int s = 0; s < sw; ++s) {
+            if (h->hctr[s].nonfinite) return JEVD_ENONFINITE;
+            if (h->hctr[s].rotations == 0) return JEVD_OK;
+        }
+        return JEVD_ENOCONV;
+    }
+    // one kernel launch per parallel step, one counter read-back per sweep
+    HIP_TRY(hipMemsetAsync(h->dctr, 0, sizeof(SweepCounters) * o.max_sweeps, h->stream));
+    for (int s = 0; s < o.max_sweeps; ++s) {
+        for (int k = 0; k < nsteps; ++k) {
+            PairStepArgs a{G, m, (long)ldg, V, n, (long)ldv, h->dpairs + h->hstep[k],
+                           h->hstep[k + 1] - h->hstep[k], dJ, tol, h->dctr + s};
+            HIP_TRY(launch_pair_step(a, h->stream));
+        }
+        HIP_TRY(hipMemcpyAsync(h->hctr + s, h->dctr + s, sizeof(SweepCounters), hipMemcpyDeviceToHost,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        *sweeps_done = s + 1;
+        if (h->hctr[s].nonfinite) return JEVD_ENONFINITE;
+        if (h->hctr[s].rotations == 0) return JEVD_OK;
+    }
+    return JEVD_ENOCONV;
+}
+
+int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed char *J, double tol,
+               const jevd_opts *opts, double *lambda, double *U, int ldu, double *V, int ldv,
+               int *sweeps)
+{
+    if (!h || !G) return JEVD_EINVAL;
+    jevd_opts o;
+    fill_defaults(&o);
+    if (opts) o = *opts;
+    int st = jevd_validate(m, n, ldg, J, tol, &o, U, ldu, V, ldv);
+    if (st) return st;
+    if (tol <= 0) tol = n * DBL_EPSILON;
+    std::memset(&h->info, 0, sizeof(h->info));
+    if (sweeps) *sweeps = 0;
+
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device) return JEVD_EINVAL;  // handle belongs to another device
+
+    const signed char *dJ = nullptr;
+    if (J) {
+        st = grow_device(&h->dJ, &h->capJ, (size_t)n);
+        if (st) return st;
+        HIP_TRY(hipMemcpyAsync(h->dJ, J, (size_t)n, hipMemcpyHostToDevice, h->stream));
+        dJ = h->dJ;
+    }
+    st = ensure_counters(h, o.max_sweeps);
+    if (st) return st;
+    if (V && !o.accumulate_v) HIP_TRY(launch_identity(V, n, (long)ldv, h->stream));
+
+    int variant = o.variant;
+    if (variant == JEVD_VAR_AUTO)
+        variant = auto_variant(m, n) ;
+    int sweeps_done = 0;
+    int status;
+    if (variant == JEVD_VAR_POINTWISE) {
+        status = run_pointwise(h, m, n, G, ldg, dJ, tol, o, V, ldv, &sweeps_done);
+        h->info.block = 0;
+        h->info.ordering = o.ordering;
+    } else {
+        const int b = o.block ? o.block : choose_block_width(m, n);
+        BlockRunArgs a{m, n, G, ldg, dJ, J, tol, variant == JEVD_VAR_FULL_BLOCK, b, o.max_sweeps,
+                       o.max_inner, V, ldv, h->stream, h->dctr, h->hctr};
+        status = run_block(&h->blk, a, &sweeps_done);
+        h->info.block = b;
+        h->info.ordering = JEVD_ORD_MODMODULUS;
+    }
+    if (status == JEVD_EHIP || status == JEVD_ENOMEM || status == JEVD_EINVAL) return status;
+    h->info.variant = variant;
+    h->info.sweeps = sweeps_done;
+    for (int s = 0; s < sweeps_done && s < JEVD_INFO_MAX_SWEEPS; ++s) {
+        h->info.rotations[s] = (long long)h->hctr[s].rotations;
+        h->info.clamps += (long long)h->hctr[s].clamps;
+        h->info.breakdowns += (long long)h->hctr[s].breakdowns;
+    }
+    if (lambda || U) HIP_TRY(launch_finalize(G, m, n, (long)ldg, dJ, lambda, U, (long)ldu, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (sweeps) *sweeps = sweeps_done;
+    return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,45 @@
+// Block one-sided Jacobi (Sec. 2.2-2.3, Alg. 3.4 with unpivoted Cholesky):
+// host-side driver interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+
+namespace jevd {
+
+struct BlockWorkspace {
+    double *gram = nullptr;     // per pivot, 2b x 2b (final Gram / Cholesky factor)
+    double *partial = nullptr;  // split-K partial Grams
+    double *vp = nullptr;       // per pivot, 2b x 2b accumulated transform
+    int *flags = nullptr;       // per pivot: 1 if its transform must be applied
+    int2 *pivots = nullptr;     // block pairs of every step of the block ordering
+    size_t capGram = 0, capPartial = 0, capVp = 0, capFlags = 0, capPivots = 0;
+    int tabN = -1;              // block count of the cached pivot table
+    int nsteps = 0, npiv = 0;
+};
+
+struct BlockRunArgs {
+    int m, n;
+    double *G;
+    int ldg;
+    const signed char *dJ;   // device, may be null
+    const signed char *hJ;   // host, may be null
+    double tol;
+    bool full_block;
+    int b;
+    int max_sweeps, max_inner;
+    double *V;
+    int ldv;
+    hipStream_t stream;
+    SweepCounters *dctr;  // max_sweeps slots, zeroed by run_block
+    SweepCounters *hctr;  // pinned mirror
+};
+
+bool block_width_supported(int b);
+bool block_shape_supported(int m, int n, int b);
+int choose_block_width(int m, int n);
+int auto_variant(int m, int n);
+int run_block(BlockWorkspace *ws, const BlockRunArgs &a, int *sweeps_done);
+void block_workspace_free(BlockWorkspace *ws);
+
+}  // namespace jevd

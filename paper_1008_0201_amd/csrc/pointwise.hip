@@ -1,0 +1,359 @@
+// Pointwise one-sided Jacobi kernels for gfx950 (Sec. 2.1).
+//
+//   k_pair_step        one parallel step: one workgroup per pivot pair; the
+//                      pair's two columns stay in registers between the Gram
+//                      pass and the rotation pass (m <= BS * CH).
+//   k_pair_step_stream the same for taller columns: the columns are read
+//                      twice (Gram pass, rotation pass).
+//   k_small_solve      a whole solve (all sweeps) of a small problem in one
+//                      workgroup, with G and V resident in LDS; used for the
+//                      row-cyclic ordering, whose pairs are strictly
+//                      sequential, and for small n.
+//   k_identity, k_finalize  V := I; lambda_i = j_i ||g_i||^2, u_i = g_i / ||g_i||.
+#include "device_math.h"
+#include "jevd_internal.h"
+
+namespace jevd {
+
+// Rotate the column pair (vp, vq) of length len with BS threads; loads of a
+// chunk of 4 strided elements are issued before the dependent stores.
+template <int BS>
+__device__ __forceinline__ void rotate_columns(double *__restrict__ vp, double *__restrict__ vq,
+                                               int len, double c, double s, bool same)
+{
+    int r = threadIdx.x;
+    for (; r + 3 * BS < len; r += 4 * BS) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = vp[r + u * BS];
+            b[u] = vq[r + u * BS];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            rotate_elems(a[u], b[u], c, s, same);
+            vp[r + u * BS] = a[u];
+            vq[r + u * BS] = b[u];
+        }
+    }
+    for (; r < len; r += BS) {
+        double a = vp[r], b = vq[r];
+        rotate_elems(a, b, c, s, same);
+        vp[r] = a;
+        vq[r] = b;
+    }
+}
+
+template <int BS, int CH>
+__global__ __launch_bounds__(BS) void k_pair_step(double *__restrict__ G, int m, long ldg,
+                                                  double *__restrict__ V, int nv, long ldv,
+                                                  const int2 *__restrict__ pairs,
+                                                  const signed char *__restrict__ J, double tol,
+                                                  SweepCounters *__restrict__ ctr)
+{
+    __shared__ double sh[3 * BS / kWave];
+    const int2 pq = pairs[blockIdx.x];
+    double *gp = G + (size_t)pq.x * ldg;
+    double *gq = G + (size_t)pq.y * ldg;
+    double xp[CH], xq[CH];
+    double app = 0.0, aqq = 0.0, apq = 0.0;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int r = threadIdx.x + k * BS;
+        xp[k] = (r < m) ? gp[r] : 0.0;
+        xq[k] = (r < m) ? gq[r] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        app = fma(xp[k], xp[k], app);
+        aqq = fma(xq[k], xq[k], aqq);
+        apq = fma(xp[k], xq[k], apq);
+    }
+    block_sum3<BS>(app, aqq, apq, sh);
+    if (!finite3(app, aqq, apq)) {
+        if (threadIdx.x == 0) atomicOr(&ctr->nonfinite, 1u);
+        return;
+    }
+    if (!needs_rotation(app, aqq, apq, tol)) return;
+    const bool same = (J == nullptr) || (J[pq.x] == J[pq.y]);
+    double c, s;
+    const bool clamped = transform_params(app, aqq, apq, same, c, s);
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int r = threadIdx.x + k * BS;
+        if (r < m) {
+            rotate_elems(xp[k], xq[k], c, s, same);
+            gp[r] = xp[k];
+            gq[r] = xq[k];
+        }
+    }
+    if (V) rotate_columns<BS>(V + (size_t)pq.x * ldv, V + (size_t)pq.y * ldv, nv, c, s, same);
+    if (threadIdx.x == 0) {
+        atomicAdd(&ctr->rotations, 1ull);
+        if (clamped) atomicAdd(&ctr->clamps, 1ull);
+    }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_pair_step_stream(double *__restrict__ G, int m, long ldg,
+                                                         double *__restrict__ V, int nv, long ldv,
+                                                         const int2 *__restrict__ pairs,
+                                                         const signed char *__restrict__ J,
+                                                         double tol, SweepCounters *__restrict__ ctr)
+{
+    __shared__ double sh[3 * BS / kWave];
+    const int2 pq = pairs[blockIdx.x];
+    double *gp = G + (size_t)pq.x * ldg;
+    double *gq = G + (size_t)pq.y * ldg;
+    double app = 0.0, aqq = 0.0, apq = 0.0;
+    for (int r = threadIdx.x; r < m; r += BS) {
+        const double a = gp[r], b = gq[r];
+        app = fma(a, a, app);
+        aqq = fma(b, b, aqq);
+        apq = fma(a, b, apq);
+    }
+    block_sum3<BS>(app, aqq, apq, sh);
+    if (!finite3(app, aqq, apq)) {
+        if (threadIdx.x == 0) atomicOr(&ctr->nonfinite, 1u);
+        return;
+    }
+    if (!needs_rotation(app, aqq, apq, tol)) return;
+    const bool same = (J == nullptr) || (J[pq.x] == J[pq.y]);
+    double c, s;
+    const bool clamped = transform_params(app, aqq, apq, same, c, s);
+    rotate_columns<BS>(gp, gq, m, c, s, same);
+    if (V) rotate_columns<BS>(V + (size_t)pq.x * ldv, V + (size_t)pq.y * ldv, nv, c, s, same);
+    if (threadIdx.x == 0) {
+        atomicAdd(&ctr->rotations, 1ull);
+        if (clamped) atomicAdd(&ctr->clamps, 1ull);
+    }
+}
+
+// Whole solve in one workgroup of NW wavefronts.  The pairs of each step
+// are dealt round-robin to the wavefronts; lanes of a wavefront run over the
+// rows.  If `lds_g` the m x n factor lives in LDS (leading dimension m), and
+// if `lds_v` also V (leading dimension n); otherwise they are used in place
+// in global memory.  Writes the per-sweep counters and the sweep count.
+template <int NW>
+__global__ __launch_bounds__(NW *kWave) void k_small_solve(
+    double *__restrict__ G, int m, int n, long ldg, double *__restrict__ V, long ldv,
+    const signed char *__restrict__ J, double tol, const int2 *__restrict__ pairs,
+    const int *__restrict__ step_start, int nsteps, int max_sweeps, int lds_g, int lds_v,
+    SweepCounters *__restrict__ ctr, int *__restrict__ sweeps_out)
+{
+    extern __shared__ double lds[];
+    __shared__ unsigned long long red[2 * NW];
+    __shared__ int nonfinite;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    constexpr int BS = NW * kWave;
+
+    double *g = G;
+    long lg = ldg;
+    double *v = V;
+    long lv = ldv;
+    if (lds_g) {
+        g = lds;
+        lg = m;
+        for (int c = 0; c < n; ++c)
+            for (int r = threadIdx.x; r < m; r += BS) g[r + (size_t)c * m] = G[r + (size_t)c * ldg];
+    }
+    if (V && lds_v) {
+        v = lds + (lds_g ? (size_t)m * n : 0);
+        lv = n;
+        for (int c = 0; c < n; ++c)
+            for (int r = threadIdx.x; r < n; r += BS) v[r + (size_t)c * n] = V[r + (size_t)c * ldv];
+    }
+    if (threadIdx.x == 0) nonfinite = 0;
+    __syncthreads();
+
+    int sweep = 0;
+    while (sweep < max_sweeps) {
+        unsigned long long rot = 0, ncl = 0;
+        for (int st = 0; st < nsteps; ++st) {
+            const int e0 = step_start[st], e1 = step_start[st + 1];
+            for (int e = e0 + wave; e < e1; e += NW) {
+                const int2 pq = pairs[e];
+                double *gp = g + (size_t)pq.x * lg;
+                double *gq = g + (size_t)pq.y * lg;
+                double app = 0.0, aqq = 0.0, apq = 0.0;
+                for (int r = lane; r < m; r += kWave) {
+                    const double a = gp[r], b = gq[r];
+                    app = fma(a, a, app);
+                    aqq = fma(b, b, aqq);
+                    apq = fma(a, b, apq);
+                }
+                app = wave_sum(app);
+                aqq = wave_sum(aqq);
+                apq = wave_sum(apq);
+                if (!finite3(app, aqq, apq)) {
+                    nonfinite = 1;
+                    continue;
+                }
+                if (!needs_rotation(app, aqq, apq, tol)) continue;
+                const bool same = (J == nullptr) || (J[pq.x] == J[pq.y]);
+                double c, s;
+                ncl += transform_params(app, aqq, apq, same, c, s) ? 1 : 0;
+                for (int r = lane; r < m; r += kWave) {
+                    double a = gp[r], b = gq[r];
+                    rotate_elems(a, b, c, s, same);
+                    gp[r] = a;
+                    gq[r] = b;
+                }
+                if (V) {
+                    double *vp = v + (size_t)pq.x * lv;
+                    double *vq = v + (size_t)pq.y * lv;
+                    for (int r = lane; r < n; r += kWave) {
+                        double a = vp[r], b = vq[r];
+                        rotate_elems(a, b, c, s, same);
+                        vp[r] = a;
+                        vq[r] = b;
+                    }
+                }
+                ++rot;
+            }
+            if constexpr (NW > 1) __syncthreads();
+        }
+        if (lane == 0) {
+            red[wave] = rot;
+            red[NW + wave] = ncl;
+        }
+        __syncthreads();
+        unsigned long long tot = 0, totc = 0;
+        for (int i = 0; i < NW; ++i) {
+            tot += red[i];
+            totc += red[NW + i];
+        }
+        const int nf = nonfinite;
+        if (threadIdx.x == 0) {
+            ctr[sweep].rotations = tot;
+            ctr[sweep].clamps = totc;
+            ctr[sweep].nonfinite = nf;
+        }
+        ++sweep;
+        __syncthreads();
+        if (tot == 0 || nf) break;
+    }
+    if (lds_g)
+        for (int c = 0; c < n; ++c)
+            for (int r = threadIdx.x; r < m; r += BS) G[r + (size_t)c * ldg] = g[r + (size_t)c * m];
+    if (V && lds_v)
+        for (int c = 0; c < n; ++c)
+            for (int r = threadIdx.x; r < n; r += BS) V[r + (size_t)c * ldv] = v[r + (size_t)c * n];
+    if (threadIdx.x == 0) *sweeps_out = sweep;
+}
+
+__global__ void k_identity(double *__restrict__ V, int n, long ldv)
+{
+    const int c = blockIdx.x;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) V[r + (size_t)c * ldv] = (r == c) ? 1.0 : 0.0;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_finalize(const double *__restrict__ G, int m, long ldg,
+                                                 const signed char *__restrict__ J,
+                                                 double *__restrict__ lambda, double *U, long ldu)
+{
+    __shared__ double sh[3 * BS / kWave];
+    const int c = blockIdx.x;
+    const double *gc = G + (size_t)c * ldg;
+    double s = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int r = threadIdx.x; r < m; r += BS) s = fma(gc[r], gc[r], s);
+    block_sum3<BS>(s, d1, d2, sh);
+    if (lambda && threadIdx.x == 0) lambda[c] = (J && J[c] < 0) ? -s : s;
+    if (U) {
+        const double nrm = sqrt(s);
+        double *uc = U + (size_t)c * ldu;
+        // U may alias G: every element is read before it is written by the same thread
+        for (int r = threadIdx.x; r < m; r += BS) uc[r] = (s > 0.0) ? gc[r] / nrm : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+template <int BS>
+static hipError_t launch_pair_step_bs(const PairStepArgs &a, hipStream_t st)
+{
+    const int ch = (a.m + BS - 1) / BS;
+    dim3 grid(a.npairs), block(BS);
+    if (ch <= 1)
+        k_pair_step<BS, 1><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+    else if (ch <= 2)
+        k_pair_step<BS, 2><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+    else if (ch <= 4)
+        k_pair_step<BS, 4><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+    else if (ch <= 8)
+        k_pair_step<BS, 8><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+    else if (ch <= 16)
+        k_pair_step<BS, 16><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+    else
+        k_pair_step_stream<BS><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_step(const PairStepArgs &a, hipStream_t st)
+{
+    if (a.npairs <= 0) return hipSuccess;
+    if (a.m > 512) return launch_pair_step_bs<256>(a, st);
+    if (a.m > 128) return launch_pair_step_bs<128>(a, st);
+    return launch_pair_step_bs<64>(a, st);
+}
+
+size_t small_solve_lds_bytes(int m, int n, bool want_v, int *lds_g, int *lds_v)
+{
+    const size_t g = (size_t)m * n * sizeof(double);
+    const size_t v = want_v ? (size_t)n * n * sizeof(double) : 0;
+    *lds_g = *lds_v = 0;
+    if (g + v <= kSmallSolveLdsBytes) {
+        *lds_g = 1;
+        *lds_v = want_v ? 1 : 0;
+        return g + v;
+    }
+    if (g <= kSmallSolveLdsBytes) {
+        *lds_g = 1;
+        return g;
+    }
+    return 0;
+}
+
+template <int NW>
+static hipError_t launch_small_nw(const SmallSolveArgs &a, hipStream_t st)
+{
+    int lg = 0, lv = 0;
+    const size_t bytes = small_solve_lds_bytes(a.m, a.n, a.V != nullptr, &lg, &lv);
+    if (bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_small_solve<NW>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    k_small_solve<NW><<<1, NW * kWave, bytes, st>>>(a.G, a.m, a.n, a.ldg, a.V, a.ldv, a.J, a.tol,
+                                                    a.pairs, a.step_start, a.nsteps, a.max_sweeps,
+                                                    lg, lv, a.ctr, a.sweeps_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_solve(const SmallSolveArgs &a, hipStream_t st)
+{
+    // one wavefront for strictly sequential orderings; otherwise up to 16
+    if (a.max_pairs_per_step <= 1) return launch_small_nw<1>(a, st);
+    if (a.max_pairs_per_step <= 4) return launch_small_nw<4>(a, st);
+    if (a.max_pairs_per_step <= 8) return launch_small_nw<8>(a, st);
+    return launch_small_nw<16>(a, st);
+}
+
+hipError_t launch_identity(double *V, int n, long ldv, hipStream_t st)
+{
+    k_identity<<<n, 256, 0, st>>>(V, n, ldv);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *G, int m, int n, long ldg, const signed char *J,
+                           double *lambda, double *U, long ldu, hipStream_t st)
+{
+    if (m > 512)
+        k_finalize<256><<<n, 256, 0, st>>>(G, m, ldg, J, lambda, U, ldu);
+    else
+        k_finalize<64><<<n, 64, 0, st>>>(G, m, ldg, J, lambda, U, ldu);
+    return hipGetLastError();
+}
+
+}  // namespace jevd

@@ -1,0 +1,199 @@
+"""Thin ctypes binding of libjevd.so (include/jevd.h).
+
+The functions below carry the names of the C entry points and only marshal
+arguments: every step of the solve runs in the HIP library.  There is no CPU
+fallback: if libjevd.so is missing or cannot be loaded, loading raises.
+PyTorch is used only for device memory and streams (``evd``).
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjevd.so")
+
+JEVD_OK, JEVD_EINVAL, JEVD_ENONFINITE, JEVD_ENOCONV, JEVD_EHIP, JEVD_ENOMEM = 0, -1, -2, -3, -4, -5
+ORD_ROWCYCLIC, ORD_MODULUS, ORD_MODMODULUS = 0, 1, 2
+VAR_POINTWISE, VAR_BLOCK_ORIENTED, VAR_FULL_BLOCK, VAR_AUTO = 0, 1, 2, 3
+INFO_MAX_SWEEPS = 64
+
+EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "jevd_validate",
+           "jevd_get_info", "jevd_strerror", "jevd_ordering")
+
+
+class jevd_opts(ctypes.Structure):
+    _fields_ = [("ordering", ctypes.c_int), ("variant", ctypes.c_int), ("block", ctypes.c_int),
+                ("max_sweeps", ctypes.c_int), ("max_inner", ctypes.c_int),
+                ("accumulate_v", ctypes.c_int)]
+
+
+class jevd_info(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int), ("variant", ctypes.c_int), ("block", ctypes.c_int),
+                ("ordering", ctypes.c_int), ("rotations", ctypes.c_longlong * INFO_MAX_SWEEPS),
+                ("clamps", ctypes.c_longlong), ("breakdowns", ctypes.c_longlong)]
+
+
+class JevdError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (what or "jevd", jevd_strerror(status), status))
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    """Load libjevd.so; raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libjevd.so not found at %s: build it with "
+                              "python -c 'import __graft_entry__ as g; g.build()'" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.jevd_default_opts.argtypes = [ctypes.POINTER(jevd_opts)]
+        L.jevd_create.argtypes = [ctypes.POINTER(_vp), _vp]
+        L.jevd_destroy.argtypes = [_vp]
+        L.jacobi_evd.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp,
+                                 ctypes.c_double, ctypes.POINTER(jevd_opts), _vp, _vp, ctypes.c_int,
+                                 _vp, ctypes.c_int, _ip]
+        L.jevd_validate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double,
+                                    ctypes.POINTER(jevd_opts), _vp, ctypes.c_int, _vp, ctypes.c_int]
+        L.jevd_get_info.argtypes = [_vp, ctypes.POINTER(jevd_info)]
+        L.jevd_strerror.argtypes = [ctypes.c_int]
+        L.jevd_strerror.restype = ctypes.c_char_p
+        L.jevd_ordering.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _ip, _ip, _ip]
+        for name in EXPORTS:
+            if name != "jevd_strerror":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------ C entry points
+def jevd_default_opts():
+    o = jevd_opts()
+    lib().jevd_default_opts(ctypes.byref(o))
+    return o
+
+
+def jevd_strerror(status):
+    return lib().jevd_strerror(int(status)).decode()
+
+
+def jevd_create(stream=0):
+    h = _vp()
+    st = lib().jevd_create(ctypes.byref(h), _vp(int(stream)) if stream else None)
+    if st != JEVD_OK:
+        raise JevdError(st, "jevd_create")
+    return h
+
+
+def jevd_destroy(h):
+    return lib().jevd_destroy(h)
+
+
+def jacobi_evd(h, m, n, G_ptr, ldg, J_host, tol, opts, lambda_ptr, U_ptr, ldu, V_ptr, ldv):
+    """Raw call with device pointers (ints) and a host J (bytes-like of int8 or
+    None).  Returns (status, sweeps)."""
+    sweeps = ctypes.c_int(0)
+    Jbuf = None
+    if J_host is not None:
+        Jbuf = (ctypes.c_byte * n).from_buffer_copy(bytes(J_host))
+    st = lib().jacobi_evd(h, m, n, _vp(G_ptr), ldg, ctypes.cast(Jbuf, _vp) if Jbuf is not None else None,
+                          float(tol), ctypes.byref(opts) if opts is not None else None,
+                          _vp(lambda_ptr) if lambda_ptr else None, _vp(U_ptr) if U_ptr else None,
+                          ldu, _vp(V_ptr) if V_ptr else None, ldv, ctypes.byref(sweeps))
+    return st, sweeps.value
+
+
+def jevd_validate(m, n, ldg, J_host, tol, opts, has_U, ldu, has_V, ldv):
+    Jbuf = None
+    if J_host is not None:
+        Jbuf = (ctypes.c_byte * len(J_host)).from_buffer_copy(bytes(J_host))
+    return lib().jevd_validate(m, n, ldg, ctypes.cast(Jbuf, _vp) if Jbuf is not None else None,
+                               float(tol), ctypes.byref(opts) if opts is not None else None,
+                               _vp(8) if has_U else None, ldu, _vp(8) if has_V else None, ldv)
+
+
+def jevd_get_info(h):
+    info = jevd_info()
+    st = lib().jevd_get_info(h, ctypes.byref(info))
+    if st != JEVD_OK:
+        raise JevdError(st, "jevd_get_info")
+    return info
+
+
+def jevd_ordering(n, ordering):
+    """Steps of 0-based pairs, as the solver runs them (host only)."""
+    ns, npr = ctypes.c_int(0), ctypes.c_int(0)
+    st = lib().jevd_ordering(n, ordering, None, None, ctypes.byref(ns), ctypes.byref(npr))
+    if st != JEVD_OK:
+        raise JevdError(st, "jevd_ordering")
+    starts = (ctypes.c_int * (ns.value + 1))()
+    pairs = (ctypes.c_int * max(1, 2 * npr.value))()
+    lib().jevd_ordering(n, ordering, starts, pairs, None, None)
+    return [[(pairs[2 * e], pairs[2 * e + 1]) for e in range(starts[k], starts[k + 1])]
+            for k in range(ns.value)]
+
+
+# ----------------------------------------------------------- torch front end
+class Solver:
+    """Owns a handle bound to the current device and torch's current stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("jevd needs a ROCm GPU; none is visible")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        self.h = jevd_create(s.cuda_stream)
+
+    def close(self):
+        if self.h:
+            jevd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def evd(self, G, J=None, tol=0.0, ordering=ORD_MODMODULUS, variant=VAR_AUTO, block=0,
+            max_sweeps=50, max_inner=30, want_U=True, want_V=True, V0=None, check=True):
+        """Solve in place on the device tensor G (float64, column-major: pass
+        a tensor whose .T is contiguous, or any (m, n) tensor with stride
+        (1, ldg)).  Returns (lam, U, V, sweeps, status)."""
+        import torch
+        if G.dtype != torch.float64 or not G.is_cuda:
+            raise TypeError("G must be a float64 device tensor")
+        m, n = G.shape
+        if G.stride(0) != 1:
+            raise ValueError("G must be column-major (stride(0) == 1)")
+        ldg = G.stride(1) if n > 1 else m
+        dev = G.device
+        lam = torch.empty(n, dtype=torch.float64, device=dev)
+        U = torch.empty((n, m), dtype=torch.float64, device=dev).T if want_U else None
+        V = None
+        o = jevd_default_opts()
+        o.ordering, o.variant, o.block = ordering, variant, block
+        o.max_sweeps, o.max_inner = max_sweeps, max_inner
+        if V0 is not None:
+            V = V0
+            o.accumulate_v = 1
+        elif want_V:
+            V = torch.empty((n, n), dtype=torch.float64, device=dev).T
+        Jb = None
+        if J is not None:
+            import numpy as np
+            Jb = np.ascontiguousarray(np.asarray(J.cpu() if hasattr(J, "cpu") else J).astype(np.int8)).tobytes()
+        st, sweeps = jacobi_evd(self.h, m, n, G.data_ptr(), ldg, Jb, tol, o, lam.data_ptr(),
+                                U.data_ptr() if U is not None else 0, m,
+                                V.data_ptr() if V is not None else 0, n if V is None else V.stride(1))
+        if check and st not in (JEVD_OK,):
+            raise JevdError(st, "jacobi_evd")
+        return lam, U, V, sweeps, st
+
+    def info(self):
+        return jevd_get_info(self.h)
