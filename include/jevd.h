@@ -77,6 +77,14 @@ typedef struct {
 
 /* Per-call diagnostics of the last jacobi_evd on a handle. */
 #define JEVD_INFO_MAX_SWEEPS 64
+/* Kernel classes of the per-kernel timings. */
+enum {
+    JEVD_K_PAIR_STEP = 0,    /* pointwise: one parallel step (or the one-workgroup solve) */
+    JEVD_K_GRAM = 1,         /* block: pivot Grams G_P^T G_P */
+    JEVD_K_PIVOT_SOLVE = 2,  /* block: Cholesky + inner sweeps per pivot */
+    JEVD_K_UPDATE = 3,       /* block: G_P <- G_P V_P and V(:,P) <- V(:,P) V_P */
+    JEVD_K_CLASSES = 4
+};
 typedef struct {
     int sweeps;                                    /* same as the *sweeps output */
     int variant;                                   /* variant actually run */
@@ -85,6 +93,10 @@ typedef struct {
     long long rotations[JEVD_INFO_MAX_SWEEPS];     /* rotations applied per sweep */
     long long clamps;                              /* hyperbolic transforms clamped to |tanh| = 0.9 */
     long long breakdowns;                          /* block pivots whose Cholesky broke down */
+    /* Filled only when timing is on (jevd_set_timing): summed HIP-event
+     * durations of each kernel class and the number of its launches. */
+    double kernel_ms[JEVD_K_CLASSES];
+    long long kernel_launches[JEVD_K_CLASSES];
 } jevd_info;
 
 /* Fills *o with the defaults listed above.  Never fails for a non-NULL o. */
@@ -131,6 +143,13 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
 int jevd_validate(int m, int n, int ldg, const signed char *J, double tol, const jevd_opts *opts,
                   const double *U, int ldu, const double *V, int ldv);
 
+/* Turns kernel timing on (1) or off (0) for later calls on h: two HIP
+ * events on the handle's stream bracket each timed group of launches (all
+ * parallel-step launches of a sweep, or a single block-path launch) and the
+ * durations are summed into jevd_info.kernel_ms / kernel_launches.  A
+ * group's time includes the dispatch gaps between its launches.  Default off. */
+int jevd_set_timing(jevd_handle_t h, int on);
+
 /* Diagnostics of the last jacobi_evd call on h. */
 int jevd_get_info(jevd_handle_t h, jevd_info *info);
 
@@ -139,7 +158,10 @@ const char *jevd_strerror(int status);
 
 /*
  * Host-only helper: the pivot ordering the solver runs (Sec. 2.4, Alg. 3.1),
- * as 0-based pairs (i < j) grouped in steps.  step_start (nsteps + 1 ints)
+ * as 0-based pairs (i < j) grouped in steps, each step's pairs in the order
+ * they are dealt to workgroups (for the modified modulus ordering on even n:
+ * the processes of the ring of Alg. 3.1, arranged so that neighbouring
+ * processes share an XCD).  step_start (nsteps + 1 ints)
  * and pairs (2 ints per pair) may be NULL to query sizes; *nsteps and
  * *npairs receive the counts.  Pairs of a step are disjoint.  No device work.
  */

@@ -27,6 +27,8 @@ struct jevd_handle_s {
     int capCtr = 0;
     int *dsweeps = nullptr;
     int *hsweeps = nullptr;  // pinned
+    unsigned *dslots = nullptr;  // per-slot rotation / clamp counts of a sweep
+    size_t capSlots = 0;
 
     // cached ordering table
     int tabN = -1, tabOrd = -1;
@@ -38,6 +40,7 @@ struct jevd_handle_s {
     size_t capStep = 0;
 
     BlockWorkspace blk;
+    KernelTimer timer;
     jevd_info info;
 };
 
@@ -211,8 +214,17 @@ int jevd_destroy(jevd_handle_t h)
     if (h->hsweeps) (void)hipHostFree(h->hsweeps);
     if (h->dpairs) (void)hipFree(h->dpairs);
     if (h->dstep) (void)hipFree(h->dstep);
+    if (h->dslots) (void)hipFree(h->dslots);
     block_workspace_free(&h->blk);
+    h->timer.release();
     delete h;
+    return JEVD_OK;
+}
+
+int jevd_set_timing(jevd_handle_t h, int on)
+{
+    if (!h || (on != 0 && on != 1)) return JEVD_EINVAL;
+    h->timer.on = on != 0;
     return JEVD_OK;
 }
 
@@ -237,11 +249,14 @@ static int run_pointwise(jevd_handle_t h, int m, int n, double *G, int ldg, cons
         HIP_TRY(hipMemsetAsync(h->dctr, 0, sizeof(SweepCounters) * o.max_sweeps, h->stream));
         SmallSolveArgs a{G, m, n, (long)ldg, V, (long)ldv, dJ, tol, h->dpairs, h->dstep, nsteps,
                          h->maxPairsPerStep, o.max_sweeps, h->dctr, h->dsweeps};
+        HIP_TRY(h->timer.begin(h->stream, JEVD_K_PAIR_STEP));
         HIP_TRY(launch_small_solve(a, h->stream));
+        HIP_TRY(h->timer.end(h->stream));
         HIP_TRY(hipMemcpyAsync(h->hsweeps, h->dsweeps, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipMemcpyAsync(h->hctr, h->dctr, sizeof(SweepCounters) * o.max_sweeps,
                                hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(h->timer.collect());
         const int sw = *h->hsweeps;
         *sweeps_done = sw;
         for (int s = 0; s < sw; ++s) {
@@ -252,15 +267,28 @@ static int run_pointwise(jevd_handle_t h, int m, int n, double *G, int ldg, cons
     }
     // one kernel launch per parallel step, one counter read-back per sweep
     HIP_TRY(hipMemsetAsync(h->dctr, 0, sizeof(SweepCounters) * o.max_sweeps, h->stream));
+    const int nslots = h->maxPairsPerStep;
+    st = grow_device(&h->dslots, &h->capSlots, (size_t)2 * nslots);
+    if (st) return st;
+    HIP_TRY(hipMemsetAsync(h->dslots, 0, sizeof(unsigned) * 2 * nslots, h->stream));
+    const long long pairs_per_sweep = h->hstep[nsteps];
     for (int s = 0; s < o.max_sweeps; ++s) {
+        // prefetch the V pair while more than a quarter of the pairs rotate
+        const bool pf = s == 0 || 4 * (long long)h->hctr[s - 1].rotations > pairs_per_sweep;
+        // the launches of a sweep are timed as one group (no events between them)
+        HIP_TRY(h->timer.begin(h->stream, JEVD_K_PAIR_STEP));
         for (int k = 0; k < nsteps; ++k) {
             PairStepArgs a{G, m, (long)ldg, V, n, (long)ldv, h->dpairs + h->hstep[k],
-                           h->hstep[k + 1] - h->hstep[k], dJ, tol, h->dctr + s};
+                           h->hstep[k + 1] - h->hstep[k], dJ, tol, h->dctr + s, pf,
+                           h->dslots, h->dslots + nslots};
             HIP_TRY(launch_pair_step(a, h->stream));
         }
+        HIP_TRY(h->timer.end(h->stream, nsteps));
+        HIP_TRY(launch_sum_slots(h->dslots, h->dslots + nslots, nslots, h->dctr + s, h->stream));
         HIP_TRY(hipMemcpyAsync(h->hctr + s, h->dctr + s, sizeof(SweepCounters), hipMemcpyDeviceToHost,
                                h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(h->timer.collect());
         *sweeps_done = s + 1;
         if (h->hctr[s].nonfinite) return JEVD_ENONFINITE;
         if (h->hctr[s].rotations == 0) return JEVD_OK;
@@ -280,6 +308,7 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
     if (st) return st;
     if (tol <= 0) tol = n * DBL_EPSILON;
     std::memset(&h->info, 0, sizeof(h->info));
+    h->timer.reset();
     if (sweeps) *sweeps = 0;
 
     int dev = 0;
@@ -309,7 +338,7 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
     } else {
         const int b = o.block ? o.block : choose_block_width(m, n);
         BlockRunArgs a{m, n, G, ldg, dJ, J, tol, variant == JEVD_VAR_FULL_BLOCK, b, o.max_sweeps,
-                       o.max_inner, V, ldv, h->stream, h->dctr, h->hctr};
+                       o.max_inner, V, ldv, h->stream, h->dctr, h->hctr, &h->timer};
         status = run_block(&h->blk, a, &sweeps_done);
         h->info.block = b;
         h->info.ordering = JEVD_ORD_MODMODULUS;
@@ -324,6 +353,10 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
     }
     if (lambda || U) HIP_TRY(launch_finalize(G, m, n, (long)ldg, dJ, lambda, U, (long)ldu, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int c = 0; c < JEVD_K_CLASSES; ++c) {
+        h->info.kernel_ms[c] = h->timer.ms[c];
+        h->info.kernel_launches[c] = h->timer.launches[c];
+    }
     if (sweeps) *sweeps = sweeps_done;
     return status;
 }

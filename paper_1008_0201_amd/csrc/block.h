@@ -4,18 +4,16 @@
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
+#include "jevd_internal.h"
 
 namespace jevd {
 
 struct BlockWorkspace {
-    double *gram = nullptr;     // per pivot, 2b x 2b (final Gram / Cholesky factor)
-    double *partial = nullptr;  // split-K partial Grams
-    double *vp = nullptr;       // per pivot, 2b x 2b accumulated transform
+    double *partial = nullptr;  // split-K partial Grams, per pivot nsplit x (W x W)
+    double *vp = nullptr;       // per pivot W x W accumulated transform, row-major
     int *flags = nullptr;       // per pivot: 1 if its transform must be applied
-    int2 *pivots = nullptr;     // block pairs of every step of the block ordering
-    size_t capGram = 0, capPartial = 0, capVp = 0, capFlags = 0, capPivots = 0;
-    int tabN = -1;              // block count of the cached pivot table
-    int nsteps = 0, npiv = 0;
+    size_t capPartial = 0, capVp = 0, capFlags = 0;
+    void *tables = nullptr;     // block and inner orderings (device copies)
 };
 
 struct BlockRunArgs {
@@ -33,6 +31,7 @@ struct BlockRunArgs {
     hipStream_t stream;
     SweepCounters *dctr;  // max_sweeps slots, zeroed by run_block
     SweepCounters *hctr;  // pinned mirror
+    KernelTimer *timer;
 };
 
 bool block_width_supported(int b);

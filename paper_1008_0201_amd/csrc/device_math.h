@@ -88,13 +88,41 @@ __device__ __forceinline__ void rotate_elems(double &x, double &y, double c, dou
     }
 }
 
-// Butterfly sum over the 64 lanes of a wavefront; every lane ends with the
-// total, summed in the same order on every lane (deterministic).
+// DPP lane permutation of a double (both 32-bit halves moved alike).
+// CTRL: 0xB1 quad_perm [1,0,3,2] (lane ^ 1), 0x4E quad_perm [2,3,0,1]
+// (lane ^ 2), 0x141 row_half_mirror (i <-> 7-i within 8 lanes), 0x140
+// row_mirror (i <-> 15-i within 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront; every lane ends with the same total.
+// Within each row of 16 lanes a butterfly of DPP moves (xor 1, xor 2, then
+// the half-mirror and mirror, which pair the two quads and the two halves);
+// the four row sums are then read from lanes 0, 16, 32, 48 and added as
+// (r0 + r1) + (r2 + r3).  Every lane adds the same operands in the same
+// order, so the result is identical on all lanes and from run to run.
+// All 64 lanes must be active.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
+    v += dpp_move<0xB1>(v);
+    v += dpp_move<0x4E>(v);
+    v += dpp_move<0x141>(v);
+    v += dpp_move<0x140>(v);
+    const double r0 = read_lane(v, 0), r1 = read_lane(v, 16);
+    const double r2 = read_lane(v, 32), r3 = read_lane(v, 48);
+    return (r0 + r1) + (r2 + r3);
 }
 
 // Sum of three values over a workgroup of BS threads; every thread gets the

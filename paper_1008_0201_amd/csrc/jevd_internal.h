@@ -20,7 +20,10 @@ struct PairStepArgs {
     int npairs;
     const signed char *J;  // device, may be null (J = I)
     double tol;
-    SweepCounters *ctr;
+    SweepCounters *ctr;     // the sweep's counters (non-finite flag)
+    bool prefetch_v;        // load the V pair with the G pair (most pairs rotate)
+    unsigned *slot_rot;     // per workgroup slot: rotations in this sweep
+    unsigned *slot_clamp;   // per workgroup slot: clamped hyperbolic transforms
 };
 
 struct SmallSolveArgs {
@@ -40,8 +43,98 @@ struct SmallSolveArgs {
     int *sweeps_out;     // device
 };
 
+// Optional kernel timing: a timed group of launches of one kernel class
+// (one launch, or all launches of a sweep) is bracketed by a pair of HIP
+// events on the stream; collect() (after a stream synchronisation) sums the
+// durations and launch counts per class and recycles the events.
+struct KernelTimer {
+    bool on = false;
+    hipEvent_t *ev = nullptr;  // 2 per timed launch
+    int *cls = nullptr;
+    int *cnt = nullptr;  // launches in each timed group
+    int cap = 0, used = 0;
+    double ms[4] = {0, 0, 0, 0};
+    long long launches[4] = {0, 0, 0, 0};
+
+    hipError_t begin(hipStream_t st, int c)
+    {
+        if (!on) return hipSuccess;
+        if (used == cap) {
+            const int ncap = cap ? 2 * cap : 256;
+            hipEvent_t *nev = new hipEvent_t[2 * ncap];
+            int *ncls = new int[ncap];
+            int *ncnt = new int[ncap];
+            for (int i = 0; i < 2 * cap; ++i) nev[i] = ev[i];
+            for (int i = 0; i < cap; ++i) {
+                ncls[i] = cls[i];
+                ncnt[i] = cnt[i];
+            }
+            for (int i = 2 * cap; i < 2 * ncap; ++i) {
+                hipError_t e = hipEventCreate(&nev[i]);
+                if (e != hipSuccess) {
+                    for (int j = 2 * cap; j < i; ++j) (void)hipEventDestroy(nev[j]);
+                    delete[] nev;
+                    delete[] ncls;
+                    delete[] ncnt;
+                    return e;
+                }
+            }
+            delete[] ev;
+            delete[] cls;
+            delete[] cnt;
+            ev = nev;
+            cls = ncls;
+            cnt = ncnt;
+            cap = ncap;
+        }
+        cls[used] = c;
+        return hipEventRecord(ev[2 * used], st);
+    }
+    hipError_t end(hipStream_t st, int nlaunch = 1)
+    {
+        if (!on) return hipSuccess;
+        hipError_t e = hipEventRecord(ev[2 * used + 1], st);
+        cnt[used] = nlaunch;
+        ++used;
+        return e;
+    }
+    hipError_t collect()
+    {
+        for (int i = 0; i < used; ++i) {
+            float t = 0.f;
+            hipError_t e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+            if (e != hipSuccess) return e;
+            ms[cls[i]] += t;
+            launches[cls[i]] += cnt[i];
+        }
+        used = 0;
+        return hipSuccess;
+    }
+    void reset()
+    {
+        used = 0;
+        for (int i = 0; i < 4; ++i) {
+            ms[i] = 0;
+            launches[i] = 0;
+        }
+    }
+    void release()
+    {
+        for (int i = 0; i < 2 * cap; ++i) (void)hipEventDestroy(ev[i]);
+        delete[] ev;
+        delete[] cls;
+        delete[] cnt;
+        ev = nullptr;
+        cls = nullptr;
+        cnt = nullptr;
+        cap = used = 0;
+    }
+};
+
 hipError_t launch_pair_step(const PairStepArgs &a, hipStream_t st);
 hipError_t launch_small_solve(const SmallSolveArgs &a, hipStream_t st);
+hipError_t launch_sum_slots(unsigned *slot_rot, unsigned *slot_clamp, int nslots,
+                            SweepCounters *ctr, hipStream_t st);
 size_t small_solve_lds_bytes(int m, int n, bool want_v, int *lds_g, int *lds_v);
 hipError_t launch_identity(double *V, int n, long ldv, hipStream_t st);
 hipError_t launch_finalize(const double *G, int m, int n, long ldg, const signed char *J,

@@ -44,24 +44,42 @@ __device__ __forceinline__ void rotate_columns(double *__restrict__ vp, double *
     }
 }
 
-template <int BS, int CH>
+// PF: the V pair (nv <= BS * CH rows) is loaded together with the G pair,
+// before the rotation decision, so that both loads are in flight at once;
+// worth it when most pairs of the sweep rotate.
+template <int BS, int CH, bool PF>
 __global__ __launch_bounds__(BS) void k_pair_step(double *__restrict__ G, int m, long ldg,
                                                   double *__restrict__ V, int nv, long ldv,
                                                   const int2 *__restrict__ pairs,
                                                   const signed char *__restrict__ J, double tol,
-                                                  SweepCounters *__restrict__ ctr)
+                                                  SweepCounters *__restrict__ ctr,
+                                                  unsigned *__restrict__ slot_rot,
+                                                  unsigned *__restrict__ slot_clamp)
 {
     __shared__ double sh[3 * BS / kWave];
     const int2 pq = pairs[blockIdx.x];
     double *gp = G + (size_t)pq.x * ldg;
     double *gq = G + (size_t)pq.y * ldg;
     double xp[CH], xq[CH];
+    double wp[PF ? CH : 1], wq[PF ? CH : 1];
+    double *vp = V ? V + (size_t)pq.x * ldv : nullptr;
+    double *vq = V ? V + (size_t)pq.y * ldv : nullptr;
     double app = 0.0, aqq = 0.0, apq = 0.0;
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
         const int r = threadIdx.x + k * BS;
         xp[k] = (r < m) ? gp[r] : 0.0;
         xq[k] = (r < m) ? gq[r] : 0.0;
+    }
+    if constexpr (PF) {
+        if (V) {
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int r = threadIdx.x + k * BS;
+                wp[k] = (r < nv) ? vp[r] : 0.0;
+                wq[k] = (r < nv) ? vq[r] : 0.0;
+            }
+        }
     }
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
@@ -71,7 +89,7 @@ __global__ __launch_bounds__(BS) void k_pair_step(double *__restrict__ G, int m,
     }
     block_sum3<BS>(app, aqq, apq, sh);
     if (!finite3(app, aqq, apq)) {
-        if (threadIdx.x == 0) atomicOr(&ctr->nonfinite, 1u);
+        if (threadIdx.x == 0) ctr->nonfinite = 1u;
         return;
     }
     if (!needs_rotation(app, aqq, apq, tol)) return;
@@ -87,10 +105,26 @@ __global__ __launch_bounds__(BS) void k_pair_step(double *__restrict__ G, int m,
             gq[r] = xq[k];
         }
     }
-    if (V) rotate_columns<BS>(V + (size_t)pq.x * ldv, V + (size_t)pq.y * ldv, nv, c, s, same);
+    if constexpr (PF) {
+        if (V) {
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int r = threadIdx.x + k * BS;
+                if (r < nv) {
+                    rotate_elems(wp[k], wq[k], c, s, same);
+                    vp[r] = wp[k];
+                    vq[r] = wq[k];
+                }
+            }
+        }
+    } else {
+        if (V) rotate_columns<BS>(vp, vq, nv, c, s, same);
+    }
     if (threadIdx.x == 0) {
-        atomicAdd(&ctr->rotations, 1ull);
-        if (clamped) atomicAdd(&ctr->clamps, 1ull);
+        // this slot is written by this workgroup only, and launches are
+        // ordered on the stream: a plain update, no atomic
+        slot_rot[blockIdx.x] += 1u;
+        if (clamped) slot_clamp[blockIdx.x] += 1u;
     }
 }
 
@@ -99,7 +133,9 @@ __global__ __launch_bounds__(BS) void k_pair_step_stream(double *__restrict__ G,
                                                          double *__restrict__ V, int nv, long ldv,
                                                          const int2 *__restrict__ pairs,
                                                          const signed char *__restrict__ J,
-                                                         double tol, SweepCounters *__restrict__ ctr)
+                                                         double tol, SweepCounters *__restrict__ ctr,
+                                                         unsigned *__restrict__ slot_rot,
+                                                         unsigned *__restrict__ slot_clamp)
 {
     __shared__ double sh[3 * BS / kWave];
     const int2 pq = pairs[blockIdx.x];
@@ -114,7 +150,7 @@ __global__ __launch_bounds__(BS) void k_pair_step_stream(double *__restrict__ G,
     }
     block_sum3<BS>(app, aqq, apq, sh);
     if (!finite3(app, aqq, apq)) {
-        if (threadIdx.x == 0) atomicOr(&ctr->nonfinite, 1u);
+        if (threadIdx.x == 0) ctr->nonfinite = 1u;
         return;
     }
     if (!needs_rotation(app, aqq, apq, tol)) return;
@@ -124,8 +160,37 @@ __global__ __launch_bounds__(BS) void k_pair_step_stream(double *__restrict__ G,
     rotate_columns<BS>(gp, gq, m, c, s, same);
     if (V) rotate_columns<BS>(V + (size_t)pq.x * ldv, V + (size_t)pq.y * ldv, nv, c, s, same);
     if (threadIdx.x == 0) {
-        atomicAdd(&ctr->rotations, 1ull);
-        if (clamped) atomicAdd(&ctr->clamps, 1ull);
+        slot_rot[blockIdx.x] += 1u;
+        if (clamped) slot_clamp[blockIdx.x] += 1u;
+    }
+}
+
+// Sum the per-slot counts of a sweep into its counters and clear the slots.
+__global__ __launch_bounds__(256) void k_sum_slots(unsigned *__restrict__ slot_rot,
+                                                   unsigned *__restrict__ slot_clamp, int nslots,
+                                                   SweepCounters *__restrict__ ctr)
+{
+    __shared__ unsigned long long sr[256], sc[256];
+    unsigned long long r = 0, c = 0;
+    for (int i = threadIdx.x; i < nslots; i += 256) {
+        r += slot_rot[i];
+        c += slot_clamp[i];
+        slot_rot[i] = 0u;
+        slot_clamp[i] = 0u;
+    }
+    sr[threadIdx.x] = r;
+    sc[threadIdx.x] = c;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            sr[threadIdx.x] += sr[threadIdx.x + h];
+            sc[threadIdx.x] += sc[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ctr->rotations += sr[0];
+        ctr->clamps += sc[0];
     }
 }
 
@@ -270,23 +335,36 @@ __global__ __launch_bounds__(BS) void k_finalize(const double *__restrict__ G, i
 }
 
 // ---------------------------------------------------------------- launchers
+template <int BS, int CH>
+static void launch_ch(const PairStepArgs &a, hipStream_t st)
+{
+    dim3 grid(a.npairs), block(BS);
+    if (a.prefetch_v && a.V && a.nv <= BS * CH)
+        k_pair_step<BS, CH, true><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs,
+                                                          a.J, a.tol, a.ctr, a.slot_rot, a.slot_clamp);
+    else
+        k_pair_step<BS, CH, false><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs,
+                                                           a.J, a.tol, a.ctr, a.slot_rot, a.slot_clamp);
+}
+
 template <int BS>
 static hipError_t launch_pair_step_bs(const PairStepArgs &a, hipStream_t st)
 {
     const int ch = (a.m + BS - 1) / BS;
-    dim3 grid(a.npairs), block(BS);
     if (ch <= 1)
-        k_pair_step<BS, 1><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+        launch_ch<BS, 1>(a, st);
     else if (ch <= 2)
-        k_pair_step<BS, 2><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+        launch_ch<BS, 2>(a, st);
     else if (ch <= 4)
-        k_pair_step<BS, 4><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+        launch_ch<BS, 4>(a, st);
     else if (ch <= 8)
-        k_pair_step<BS, 8><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+        launch_ch<BS, 8>(a, st);
     else if (ch <= 16)
-        k_pair_step<BS, 16><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+        launch_ch<BS, 16>(a, st);
     else
-        k_pair_step_stream<BS><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr);
+        k_pair_step_stream<BS><<<dim3(a.npairs), dim3(BS), 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv,
+                                                                    a.pairs, a.J, a.tol, a.ctr,
+                                                                    a.slot_rot, a.slot_clamp);
     return hipGetLastError();
 }
 
@@ -338,6 +416,13 @@ hipError_t launch_small_solve(const SmallSolveArgs &a, hipStream_t st)
     if (a.max_pairs_per_step <= 4) return launch_small_nw<4>(a, st);
     if (a.max_pairs_per_step <= 8) return launch_small_nw<8>(a, st);
     return launch_small_nw<16>(a, st);
+}
+
+hipError_t launch_sum_slots(unsigned *slot_rot, unsigned *slot_clamp, int nslots,
+                            SweepCounters *ctr, hipStream_t st)
+{
+    k_sum_slots<<<1, 256, 0, st>>>(slot_rot, slot_clamp, nslots, ctr);
+    return hipGetLastError();
 }
 
 hipError_t launch_identity(double *V, int n, long ldv, hipStream_t st)

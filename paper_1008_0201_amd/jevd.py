@@ -17,7 +17,8 @@ VAR_POINTWISE, VAR_BLOCK_ORIENTED, VAR_FULL_BLOCK, VAR_AUTO = 0, 1, 2, 3
 INFO_MAX_SWEEPS = 64
 
 EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "jevd_validate",
-           "jevd_get_info", "jevd_strerror", "jevd_ordering")
+           "jevd_get_info", "jevd_set_timing", "jevd_strerror", "jevd_ordering")
+K_PAIR_STEP, K_GRAM, K_PIVOT_SOLVE, K_UPDATE = 0, 1, 2, 3
 
 
 class jevd_opts(ctypes.Structure):
@@ -29,7 +30,8 @@ class jevd_opts(ctypes.Structure):
 class jevd_info(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("variant", ctypes.c_int), ("block", ctypes.c_int),
                 ("ordering", ctypes.c_int), ("rotations", ctypes.c_longlong * INFO_MAX_SWEEPS),
-                ("clamps", ctypes.c_longlong), ("breakdowns", ctypes.c_longlong)]
+                ("clamps", ctypes.c_longlong), ("breakdowns", ctypes.c_longlong),
+                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_longlong * 4)]
 
 
 class JevdError(RuntimeError):
@@ -60,6 +62,7 @@ def lib():
         L.jevd_validate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double,
                                     ctypes.POINTER(jevd_opts), _vp, ctypes.c_int, _vp, ctypes.c_int]
         L.jevd_get_info.argtypes = [_vp, ctypes.POINTER(jevd_info)]
+        L.jevd_set_timing.argtypes = [_vp, ctypes.c_int]
         L.jevd_strerror.argtypes = [ctypes.c_int]
         L.jevd_strerror.restype = ctypes.c_char_p
         L.jevd_ordering.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _ip, _ip, _ip]
@@ -122,6 +125,12 @@ def jevd_get_info(h):
     if st != JEVD_OK:
         raise JevdError(st, "jevd_get_info")
     return info
+
+
+def jevd_set_timing(h, on):
+    st = lib().jevd_set_timing(h, 1 if on else 0)
+    if st != JEVD_OK:
+        raise JevdError(st, "jevd_set_timing")
 
 
 def jevd_ordering(n, ordering):
@@ -197,3 +206,6 @@ class Solver:
 
     def info(self):
         return jevd_get_info(self.h)
+
+    def set_timing(self, on):
+        jevd_set_timing(self.h, on)

@@ -81,3 +81,20 @@ def test_validate(args, ok):
     assert (st == 0) == ok
     if not ok:
         assert st == B.JEVD_EINVAL
+
+
+@pytest.mark.parametrize("n", [4, 16, 64, 200, 1024])
+def test_ring_table_keeps_one_column_per_slot(n):
+    """Modified modulus on even n runs the ring of Alg. 3.1: every workgroup
+    slot (a fixed ring process) keeps exactly one of its two columns from one
+    step to the next, and the processes end the sweep on the antidiagonal in
+    reverse order (the pair sets themselves are checked against the oracle
+    above)."""
+    steps = B.jevd_ordering(n, B.ORD_MODMODULUS)
+    p = n // 2
+    for k in range(n - 1):
+        for b in range(p):
+            shared = set(steps[k][b]) & set(steps[k + 1][b])
+            assert len(shared) == 1, (k, b, steps[k][b], steps[k + 1][b])
+    first = {tuple(sorted(pr)) for pr in steps[0]}
+    assert first == {(r, n - 1 - r) for r in range(p)}
