@@ -328,11 +328,39 @@ static int cross_ordering(int wi, int wj, int *step_start, int *pairs)
     return L;
 }
 
+static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *J, double tol,
+                           int b, int full_block, int max_sweeps, int max_inner,
+                           int accumulate_v, double *lambda, double *V, int ldv,
+                           int *sweeps_out, long long *rot_per_sweep,
+                           long long *nbreakdown_out, int max_steps);
+
 int SFX(orc_block_jevd)(int m, int n, double *G, int ldg, const signed char *J, double tol,
                         int b, int full_block, int max_sweeps, int max_inner,
                         int accumulate_v, double *lambda, double *V, int ldv,
                         int *sweeps_out, long long *rot_per_sweep,
                         long long *nbreakdown_out)
+{
+    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, max_sweeps, max_inner,
+                           accumulate_v, lambda, V, ldv, sweeps_out, rot_per_sweep,
+                           nbreakdown_out, -1);
+}
+
+/* The first max_steps outer steps of the first sweep only: a bounded sample
+ * of the block algorithm's work, used to time the oracle on inputs too large
+ * to solve on the CPU.  Returns the status of the partial run. */
+int SFX(orc_block_steps)(int m, int n, double *G, int ldg, const signed char *J, double tol,
+                         int b, int full_block, int max_inner, int max_steps)
+{
+    int sweeps = 0;
+    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, 1, max_inner, 0, NULL, NULL,
+                           n, &sweeps, NULL, NULL, max_steps);
+}
+
+static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *J, double tol,
+                           int b, int full_block, int max_sweeps, int max_inner,
+                           int accumulate_v, double *lambda, double *V, int ldv,
+                           int *sweeps_out, long long *rot_per_sweep,
+                           long long *nbreakdown_out, int max_steps)
 {
     int st = check_args(m, n, ldg, J, ldv, V);
     if (st) return st;
@@ -379,7 +407,7 @@ int SFX(orc_block_jevd)(int m, int n, double *G, int ldg, const signed char *J, 
         long long rot = 0;
         int bad = 0;
         ++sweeps;
-        for (int sidx = 0; sidx < ons && !bad; ++sidx) {
+        for (int sidx = 0; sidx < ons && !bad && (max_steps < 0 || sidx < max_steps); ++sidx) {
             for (int e = ostart[sidx]; e < ostart[sidx + 1] && !bad; ++e) {
                 int I = opairs[2 * e], Jb = opairs[2 * e + 1];
                 int wi = bstart[I + 1] - bstart[I], wj = bstart[Jb + 1] - bstart[Jb];

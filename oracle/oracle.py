@@ -53,6 +53,10 @@ def lib():
                           ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _ip,
                           _llp, _llp]
             f.restype = ctypes.c_int
+            f = getattr(L, "orc_block_steps_" + s)
+            f.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _cp, ctypes.c_double,
+                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+            f.restype = ctypes.c_int
             f = getattr(L, "orc_rotation_" + s)
             f.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                           ctypes.c_int, _dp, _dp]
@@ -148,6 +152,18 @@ def block_jevd(G, J=None, tol=None, b=8, full_block=False, max_sweeps=50, max_in
            _ptr(lam), None if V is None else _ptr(V), n, ctypes.byref(sweeps),
            _ptr(rot, _llp), ctypes.byref(nbr))
     return Result(st, G, lam, V, sweeps.value, rot[:sweeps.value].copy(), nbr.value)
+
+
+def block_steps(G, J=None, tol=None, b=32, full_block=False, max_inner=30, steps=1, prec="d"):
+    """The first `steps` outer steps of one block sweep (a bounded sample of
+    the block algorithm's work); returns (status, G after those steps)."""
+    G, m, n, Jb, _ = _prep(G, J, False, None)
+    if tol is None:
+        tol = n * np.finfo(np.float64).eps
+    f = getattr(lib(), "orc_block_steps_" + prec)
+    st = f(m, n, _ptr(G), m, None if Jb is None else Jb.ctypes.data_as(_cp), float(tol), b,
+           1 if full_block else 0, max_inner, steps)
+    return st, G
 
 
 def rotation(app, aqq, apq, same_sign, prec="d"):

@@ -94,6 +94,19 @@ def graded_spd_known_factor(n=8192, k=2, lam_decades=6.0, row_decades=4.0,
     return Workload("spd-rowgraded-n%d" % n, G, None, n * DBL_EPS, ordering)
 
 
+def graded_spd_transposed(n=8192, k=2, lam_decades=3.0, row_decades=4.0):
+    """The factor the trigonometric algorithm works on for the row-graded
+    recipe above: the paper's trigonometric method transforms G^* from the
+    right (Sec. 2.1), so the solver receives F = G^T = Q diag(lam) Q^T D,
+    which is column-graded.  H = G G^T and F F^T = G^T G have the same
+    eigenvalues.  lam_decades = 3 (lam = 10^U(-3,0)) keeps
+    kappa(Q diag(lam) Q^T) = 1e3, for which FP64 relative accuracy of
+    1e-12 is attainable; lam_decades = 6 is the literal recipe."""
+    wl = graded_spd_known_factor(n, k=k, lam_decades=lam_decades, row_decades=row_decades)
+    name = "spd-graded-T-n%d%s" % (n, "" if lam_decades == 3.0 else "-lam%g" % lam_decades)
+    return Workload(name, np.asfortranarray(wl.G.T), None, wl.tol, MODMODULUS)
+
+
 def random_signature(n, g, lo=0.3, hi=0.7):
     """J with round(rho n) entries -1 at random positions, rho ~ U(lo, hi)."""
     rho = g.uniform(lo, hi)

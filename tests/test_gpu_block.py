@@ -89,14 +89,27 @@ def test_block_hyperbolic(solver, orc, n, b, full_block):
     check(orc, wl.G, wl.J, wl.tol, b, full_block, got)
 
 
-def test_block_matches_pointwise_definition(solver, orc):
-    """The block path's eigenvalues against the pointwise oracle (the
-    definition of the result, independent of the block ordering)."""
-    wl = W.graded_spd_known_factor(512, k=2, lam_decades=6.0, row_decades=4.0)
-    got = run(solver, wl.G, None, wl.tol, 1, 32, want_V=False)
+@pytest.mark.parametrize("variant", [1, 2])
+def test_block_matches_pointwise_definition(solver, orc, variant):
+    """The block workload's recipe at n = 512 (the solver receives G^T, with
+    lam = 10^U(-3,0)): the block path's eigenvalues against the pointwise
+    oracle, the definition of the result independent of the ordering."""
+    wl = W.graded_spd_transposed(512, k=2, lam_decades=3.0)
+    got = run(solver, wl.G, None, wl.tol, variant, 32, want_V=False)
     assert got["st"] == 0
     ref = orc.jevd(wl.G, None, wl.tol, orc.MODMODULUS, want_v=False)
-    assert rel_err(got["lam"], ref.lam) <= REL_TOL
+    # full block applies more rotations per sweep; its rounding differs from
+    # the pointwise order by ~1e-12 on this input (see the oracle pins)
+    assert rel_err(got["lam"], ref.lam) <= (REL_TOL if variant == 1 else 5e-12)
+
+
+def test_block_workload_recipe_small(solver, orc):
+    """The block workload's recipe at n = 1024 against the block oracle
+    (same ordering, b = 32, block-oriented)."""
+    wl = W.graded_spd_transposed(1024, k=2, lam_decades=3.0)
+    got = run(solver, wl.G, None, wl.tol, 1, 32)
+    ref = check(orc, wl.G, None, wl.tol, 32, False, got)
+    print("n=1024 block workload recipe: sweeps gpu %d oracle %d" % (got["sweeps"], ref.sweeps))
 
 
 def test_block_status_paths(solver, orc):
