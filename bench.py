@@ -60,6 +60,24 @@ def make_workload(name):
     raise SystemExit("unknown workload %r" % name)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary (profiles/traffic.json), or None if absent or if the kernel's
+    sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        h = hashlib.sha256()
+        for f in rec["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != rec["source_sha256_16"]:
+            return None
+        return 1024.0 * (rec["fetch_kib_per_launch"] * rec["scale_fetch"] +
+                         rec["write_kib_per_launch"] * rec["scale_write"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def property_gate(G0, Gout, V, U, n, eps):
     """Checks that hold at any size: U orthonormal within 10 n eps, V
     orthogonal, and G_out = G_in V column by column (FP64 GEMM on the GPU;
@@ -170,7 +188,8 @@ def main():
         bytes_per_launch = pairs_per_launch * 32.0 * (m + n)
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic("k_pair_step") if wl.name == "hyperbolic-graded-n1024" else None,
                     "kernel": "k_pair_step", "avg_launch_us": round(avg_ms * 1e3, 3),
                     "bytes_per_launch": bytes_per_launch,
                     "timing": "HIP events around each sweep's launches on the solver stream; "
