@@ -45,17 +45,21 @@ __device__ __forceinline__ int pivot_col(int k, int2 IJ, int b)
 }
 
 // ------------------------------------------------------------------ k_gram
+// 32-row slabs of G_P are staged transposed in LDS (row pitch W+1), double
+// buffered: the loads of slab s+1 are in flight in registers while the
+// MFMAs of slab s run, with one barrier per slab.
 template <int W>
 __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ G, int m, long ldg, int b,
                                               const int2 *__restrict__ piv, int rows_per_split,
                                               double *__restrict__ partial)
 {
-    constexpr int KR = 32;                    // rows staged per iteration
+    constexpr int KR = 32;                    // rows staged per slab
     constexpr int LDC = W + 1;                // padded LDS row (doubles)
     constexpr int NT = W / 16;
     constexpr int NUP = NT * (NT + 1) / 2;    // upper tiles, diagonal included
     constexpr int TPW = (NUP + 3) / 4;        // tiles per wavefront
-    __shared__ double st[KR * LDC];           // st[kr][c] = G_P[r0 + kr][c]
+    constexpr int EPT = KR * W / 256;         // staged elements per thread
+    __shared__ double st[2][KR * LDC];        // st[buf][kr][c] = G_P[r0 + kr][c]
     const int pv = blockIdx.x, split = blockIdx.y;
     const int2 IJ = piv[pv];
     const int r_begin = split * rows_per_split;
@@ -80,26 +84,48 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ G, int 
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
 
+    // element u of this thread's slab share: row kr = e % KR, column c = e / KR
+    const double *colp[EPT];
+    int kr_of[EPT], c_of[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = threadIdx.x + u * 256;
+        kr_of[u] = e % KR;
+        c_of[u] = e / KR;
+        colp[u] = G + (size_t)pivot_col(c_of[u], IJ, b) * ldg;
+    }
+    double reg[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int r = r_begin + kr_of[u];
+        reg[u] = (r < r_end) ? colp[u][r] : 0.0;
+    }
+    int buf = 0;
     for (int r0 = r_begin; r0 < r_end; r0 += KR) {
-        for (int e = threadIdx.x; e < KR * W; e += 256) {
-            const int kr = e % KR, c = e / KR;
-            const int r = r0 + kr;
-            st[kr * LDC + c] = (r < r_end) ? G[(size_t)pivot_col(c, IJ, b) * ldg + r] : 0.0;
-        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) st[buf][kr_of[u] * LDC + c_of[u]] = reg[u];
         __syncthreads();
+        const int r1 = r0 + KR;
+        if (r1 < r_end) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int r = r1 + kr_of[u];
+                reg[u] = (r < r_end) ? colp[u][r] : 0.0;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < KR; k += 4) {
-            const double *row = st + (k + lane / 16) * LDC + (lane % 16);
+            const double *row = st[buf] + (k + lane / 16) * LDC + (lane % 16);
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
                 if (ti[q] >= 0) {
-                    const double a = row[ti[q] * 16];
-                    const double bb = row[tj[q] * 16];
-                    acc[q] = mfma16x16x4(a, bb, acc[q]);
+                    const double x = row[ti[q] * 16];
+                    const double y = row[tj[q] * 16];
+                    acc[q] = mfma16x16x4(x, y, acc[q]);
                 }
             }
         }
-        __syncthreads();
+        buf ^= 1;
     }
     double *out = partial + ((size_t)pv * gridDim.y + split) * W * W;
 #pragma unroll
@@ -114,32 +140,46 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ G, int 
 }
 
 // ---------------------------------------------------------- k_pivot_solve
-// Inner sweeps on the columns of X (len rows, column c at X + c * ldx) with
-// one wavefront per pair; the transform is also applied to the columns of Y
-// (ylen rows, ld ldy) when Y is not null.  Returns this thread's count of
-// rotations (counted by lane 0 of each wavefront only).
-struct InnerTables {
-    const int2 *pairs;
-    const int *start;
-    int nsteps;
-};
+// Inner orderings over the W = 2b columns of a pivot, in closed form (no
+// table reads on the critical path of an inner step):
+//   all pairs : the modified modulus ordering over W columns, W steps of
+//               W/2 pairs (modulus_pair);
+//   I x J     : the bipartite shift, b steps; step s holds (k, b + (k+s) mod b).
+__device__ __forceinline__ int inner_steps(int all_pairs, int W) { return all_pairs ? W : W / 2; }
+__device__ __forceinline__ int inner_step_pairs(int all_pairs, int W) { return W / 2; }
+__device__ __forceinline__ int2 inner_pair(int all_pairs, int W, int s, int r)
+{
+    if (all_pairs) {
+        int i, j;
+        modulus_pair(W, s + 1, r, &i, &j);
+        return make_int2(i, j);
+    }
+    const int b = W / 2;
+    return make_int2(r, b + (r + s) % b);
+}
 
+// Breakdown path: one inner sweep directly on the columns of G_P (len rows,
+// pivot-local column k at X + pivot_col(k) * ldx) and of V, one wavefront per
+// pair, lanes over rows.  rot / ncl count on lane 0 of each wavefront.
 template <int NW>
-__device__ void inner_sweep(double *X, long ldx, int len, double *Y, long ldy, int ylen,
-                            const signed char *JP, const InnerTables &tab, double tol,
-                            unsigned long long &rot, unsigned long long &ncl, int *bad)
+__device__ void inner_sweep_global(double *X, long ldx, int len, double *Y, long ldy, int ylen,
+                                   const signed char *JP, int all_pairs, int W, double tol,
+                                   int2 IJ, int b, unsigned long long &rot,
+                                   unsigned long long &ncl, int *bad)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int s = 0; s < tab.nsteps; ++s) {
-        for (int e = tab.start[s] + wave; e < tab.start[s + 1]; e += NW) {
-            const int2 pq = tab.pairs[e];
-            double *xp = X + (size_t)pq.x * ldx, *xq = X + (size_t)pq.y * ldx;
+    const int nsteps = inner_steps(all_pairs, W), npairs = inner_step_pairs(all_pairs, W);
+    for (int s = 0; s < nsteps; ++s) {
+        for (int e = wave; e < npairs; e += NW) {
+            const int2 pq = inner_pair(all_pairs, W, s, e);
+            double *xp = X + (size_t)pivot_col(pq.x, IJ, b) * ldx;
+            double *xq = X + (size_t)pivot_col(pq.y, IJ, b) * ldx;
             double app = 0.0, aqq = 0.0, apq = 0.0;
             for (int r = lane; r < len; r += 64) {
-                const double a = xp[r], c = xq[r];
-                app = fma(a, a, app);
-                aqq = fma(c, c, aqq);
-                apq = fma(a, c, apq);
+                const double x = xp[r], y = xq[r];
+                app = fma(x, x, app);
+                aqq = fma(y, y, aqq);
+                apq = fma(x, y, apq);
             }
             app = wave_sum(app);
             aqq = wave_sum(aqq);
@@ -153,18 +193,19 @@ __device__ void inner_sweep(double *X, long ldx, int len, double *Y, long ldy, i
             double c, sn;
             if (transform_params(app, aqq, apq, same, c, sn) && lane == 0) ++ncl;
             for (int r = lane; r < len; r += 64) {
-                double a = xp[r], d = xq[r];
-                rotate_elems(a, d, c, sn, same);
-                xp[r] = a;
-                xq[r] = d;
+                double x = xp[r], y = xq[r];
+                rotate_elems(x, y, c, sn, same);
+                xp[r] = x;
+                xq[r] = y;
             }
             if (Y) {
-                double *yp = Y + (size_t)pq.x * ldy, *yq = Y + (size_t)pq.y * ldy;
+                double *yp = Y + (size_t)pivot_col(pq.x, IJ, b) * ldy;
+                double *yq = Y + (size_t)pivot_col(pq.y, IJ, b) * ldy;
                 for (int r = lane; r < ylen; r += 64) {
-                    double a = yp[r], d = yq[r];
-                    rotate_elems(a, d, c, sn, same);
-                    yp[r] = a;
-                    yq[r] = d;
+                    double x = yp[r], y = yq[r];
+                    rotate_elems(x, y, c, sn, same);
+                    yp[r] = x;
+                    yq[r] = y;
                 }
             }
             if (lane == 0) ++rot;
@@ -181,7 +222,6 @@ struct PivotSolveArgs {
     int b;
     double tol;
     int all_pairs, full_block, max_inner;
-    InnerTables full, cross;
     double *vpt;  // per pivot W x W, V_P row-major
     int *flag;    // per pivot: 1 apply V_P, 0 nothing to apply
     SweepCounters *ctr;
@@ -194,13 +234,31 @@ struct PivotSolveArgs {
     long ldv;
 };
 
+// LDS pitch of the factor R: one more than W (bank spread when the lanes of
+// a wavefront read different columns at the same row).
 template <int W>
-__global__ __launch_bounds__(1024) void k_pivot_solve(PivotSolveArgs a)
+constexpr int gram_pitch() { return W + 1; }
+
+// Workgroup of the pivot solve: 4 wavefronts.  In the inner sweeps lane k of
+// every wavefront owns pair k of the step (W/2 pairs) and wavefront w owns
+// rows [w W/4, (w+1) W/4) of R and V_P: each wavefront forms partial dot
+// products over its rows, the partials meet in LDS, and every wavefront adds
+// them in wavefront order (identical totals everywhere) and computes the
+// 2x2 transforms of all pairs at once, one per lane, before rotating its rows.
+constexpr int kPivotThreads = 256;
+
+template <int W>
+__global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
 {
-    constexpr int NW = 16;
+    constexpr int NW = kPivotThreads / 64;
+    constexpr int P = gram_pitch<W>();
+    constexpr int NP = W / 2;          // pairs per inner step
+    constexpr int RPW = W / NW;        // rows of R / V_P per wavefront
+    static_assert(NP <= 64, "one pair per lane");
     extern __shared__ double lds[];
-    double *A = lds;            // W x W column-major: Gram, then R
-    double *VP = lds + W * W;   // W x W column-major
+    double *A = lds;                   // W x W column-major, pitch P: Gram, then R
+    double *VP = lds + W * P;          // W x W column-major, pitch P (first: rows of R)
+    double *red = VP + W * P;          // NW x 3 x NP partial dot products
     __shared__ signed char JP[W];
     __shared__ int s_need, s_bad, s_broke;
     __shared__ unsigned long long s_rot[NW], s_cl[NW];
@@ -215,34 +273,58 @@ __global__ __launch_bounds__(1024) void k_pivot_solve(PivotSolveArgs a)
         s_bad = 0;
         s_broke = 0;
     }
-    // A_P: sum of the split partials (upper tiles), mirrored to the lower part
-    for (int e = tid; e < W * W; e += 1024) {
-        int r = e % W, c = e / W;
-        if ((r / 16) > (c / 16) || ((r / 16) == (c / 16) && r > c)) {
-            const int t = r;
-            r = c;
-            c = t;
+    // A_P: the split partials (upper tiles) added in split order, mirrored
+    // to the lower part; 8 splits of 4 entries are loaded at a time
+    const double *base = a.partial + (size_t)pv * a.nsplit * W * W;
+    for (int e0 = tid; e0 < W * W; e0 += 4 * kPivotThreads) {
+        int off[4];
+        double acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * kPivotThreads;
+            int r = e % W, c = e / W;
+            if ((r / 16) > (c / 16) || ((r / 16) == (c / 16) && r > c)) {
+                const int t = r;
+                r = c;
+                c = t;
+            }
+            off[q] = (e < W * W) ? c * W + r : 0;
+            acc[q] = 0.0;
         }
-        const double *src = a.partial + (size_t)pv * a.nsplit * W * W + (size_t)c * W + r;
-        double s = 0.0;
-        for (int sp = 0; sp < a.nsplit; ++sp) s += src[(size_t)sp * W * W];
-        A[e] = s;
+        for (int sp0 = 0; sp0 < a.nsplit; sp0 += 8) {
+            double v[4][8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    v[q][u] = (sp0 + u < a.nsplit) ? base[(size_t)(sp0 + u) * W * W + off[q]] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (sp0 + u < a.nsplit) acc[q] += v[q][u];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * kPivotThreads;
+            if (e < W * W) A[(e / W) * P + (e % W)] = acc[q];
+        }
     }
     __syncthreads();
     // skip test on the targeted off-diagonal entries; finiteness of all
-    for (int e = tid; e < W * W; e += 1024) {
+    for (int e = tid; e < W * W; e += kPivotThreads) {
         const int r = e % W, c = e / W;
-        const double x = A[e];
+        const double x = A[c * P + r];
         if (!isfinite(x)) s_bad = 1;
         if (r < c && (a.all_pairs || (r < b && c >= b))) {
-            const double arr = A[r * W + r], acc = A[c * W + c];
-            if (arr != 0.0 && acc != 0.0 && fabs(x) > a.tol * sqrt(arr) * sqrt(acc)) s_need = 1;
+            const double arr = A[r * P + r], acc2 = A[c * P + c];
+            if (arr != 0.0 && acc2 != 0.0 && fabs(x) > a.tol * sqrt(arr) * sqrt(acc2)) s_need = 1;
         }
     }
     __syncthreads();
     if (s_bad) {
         if (tid == 0) {
-            atomicOr(&a.ctr->nonfinite, 1u);
+            a.ctr->nonfinite = 1u;
             a.flag[pv] = 0;
         }
         return;
@@ -251,104 +333,142 @@ __global__ __launch_bounds__(1024) void k_pivot_solve(PivotSolveArgs a)
         if (tid == 0) a.flag[pv] = 0;
         return;
     }
-    // Cholesky A_P = R^T R, right-looking, R kept in the upper triangle of A
+    // Cholesky A_P = R^T R, right-looking: step j writes row j of R
+    // (r_jl = a_jl / r_jj) into the VP buffer, then, after a barrier,
+    // subtracts r_ji r_jl from the trailing entries (i, l), j < i <= l.
     for (int j = 0; j < W; ++j) {
-        if (tid == 0) {
-            const double d = A[j * W + j];
-            if (d > 0.0)
-                A[j * W + j] = sqrt(d);
-            else
-                s_broke = 1;
+        const double d = A[j * P + j];
+        if (!(d > 0.0)) {
+            if (tid == 0) s_broke = 1;
+            break;  // d is the same for every thread: a uniform exit
         }
+        const double rjj = sqrt(d);
+        for (int l = j + tid; l < W; l += kPivotThreads)
+            VP[l * P + j] = (l == j) ? rjj : A[l * P + j] / rjj;
         __syncthreads();
-        if (s_broke) break;
-        const double rjj = A[j * W + j];
-        for (int l = j + 1 + tid; l < W; l += 1024) A[l * W + j] /= rjj;
-        __syncthreads();
-        for (int e = tid; e < W * W; e += 1024) {
-            const int i = e % W, l = e / W;
-            if (i > j && i <= l) A[l * W + i] -= A[i * W + j] * A[l * W + j];
+        const int nt = W - 1 - j;  // trailing order
+        for (int e = tid; e < nt * nt; e += kPivotThreads) {
+            const int i = j + 1 + e % nt, l = j + 1 + e / nt;
+            if (i <= l) A[l * P + i] -= VP[i * P + j] * VP[l * P + j];
         }
         __syncthreads();
     }
     const bool broke = s_broke != 0;
-    InnerTables tab = a.all_pairs ? a.full : a.cross;
     unsigned long long rot = 0, ncl = 0;
     int bad = 0;
     if (!broke) {
-        for (int e = tid; e < W * W; e += 1024) {
+        // R (upper) from the VP buffer into A, then V_P := I
+        for (int e = tid; e < W * W; e += kPivotThreads) {
             const int r = e % W, c = e / W;
-            if (r > c) A[e] = 0.0;
-            VP[e] = (r == c) ? 1.0 : 0.0;
+            A[c * P + r] = (r <= c) ? VP[c * P + r] : 0.0;
+        }
+        __syncthreads();
+        for (int e = tid; e < W * W; e += kPivotThreads) {
+            const int r = e % W, c = e / W;
+            VP[c * P + r] = (r == c) ? 1.0 : 0.0;
         }
         __syncthreads();
     }
     const int sweeps = a.full_block ? a.max_inner : 1;
+    const int r0w = wave * RPW;
     for (int it = 0; it < sweeps; ++it) {
-        unsigned long long r0 = rot;
+        unsigned long long rot_it = 0;
         if (!broke) {
-            inner_sweep<NW>(A, W, W, VP, W, W, JP, tab, a.tol, rot, ncl, &bad);
-        } else {
-            // G_P is transformed in place, and V with it: no V_P to apply
-            double *gbase = a.G, *vbase = a.V;
-            // columns of the pivot are not contiguous: run on the two blocks
-            // through a column map by transforming pivot-local pair indices
-            // into global ones
-            for (int s = 0; s < tab.nsteps; ++s) {
-                for (int e = tab.start[s] + wave; e < tab.start[s + 1]; e += NW) {
-                    const int2 pq = tab.pairs[e];
-                    double *xp = gbase + (size_t)pivot_col(pq.x, IJ, b) * a.ldg;
-                    double *xq = gbase + (size_t)pivot_col(pq.y, IJ, b) * a.ldg;
-                    double app = 0.0, aqq = 0.0, apq = 0.0;
-                    for (int r = lane; r < a.m; r += 64) {
-                        const double x = xp[r], y = xq[r];
-                        app = fma(x, x, app);
-                        aqq = fma(y, y, aqq);
-                        apq = fma(x, y, apq);
+            const int nsteps = inner_steps(a.all_pairs, W);
+            for (int s = 0; s < nsteps; ++s) {
+                int2 pq = make_int2(0, 1);
+                if (lane < NP) pq = inner_pair(a.all_pairs, W, s, lane);
+                const double *xp = A + pq.x * P + r0w, *xq = A + pq.y * P + r0w;
+                // partial dot products over this wavefront's rows, added as a
+                // pairwise tree (rounding grows with log2(RPW), not RPW)
+                double sxx[RPW], syy[RPW], sxy[RPW];
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    const double x = xp[r], y = xq[r];
+                    sxx[r] = x * x;
+                    syy[r] = y * y;
+                    sxy[r] = x * y;
+                }
+#pragma unroll
+                for (int h = RPW / 2; h > 0; h /= 2)
+#pragma unroll
+                    for (int r = 0; r < h; ++r) {
+                        sxx[r] += sxx[r + h];
+                        syy[r] += syy[r + h];
+                        sxy[r] += sxy[r + h];
                     }
-                    app = wave_sum(app);
-                    aqq = wave_sum(aqq);
-                    apq = wave_sum(apq);
-                    if (!finite3(app, aqq, apq)) {
-                        bad = 1;
-                        continue;
-                    }
-                    if (!needs_rotation(app, aqq, apq, a.tol)) continue;
-                    const bool same = JP[pq.x] == JP[pq.y];
-                    double c, sn;
-                    if (transform_params(app, aqq, apq, same, c, sn) && lane == 0) ++ncl;
-                    for (int r = lane; r < a.m; r += 64) {
-                        double x = xp[r], y = xq[r];
+                double app = sxx[0], aqq = syy[0], apq = sxy[0];
+                if (lane < NP) {
+                    red[(wave * 3 + 0) * NP + lane] = app;
+                    red[(wave * 3 + 1) * NP + lane] = aqq;
+                    red[(wave * 3 + 2) * NP + lane] = apq;
+                }
+                __syncthreads();
+                app = aqq = apq = 0.0;
+                if (lane < NP) {
+                    // (w0 + w1) + (w2 + w3): the same order in every wavefront
+                    static_assert(NW == 4, "four wavefronts");
+                    double t[3][NW];
+#pragma unroll
+                    for (int w = 0; w < NW; ++w)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) t[k][w] = red[(w * 3 + k) * NP + lane];
+                    app = (t[0][0] + t[0][1]) + (t[0][2] + t[0][3]);
+                    aqq = (t[1][0] + t[1][1]) + (t[1][2] + t[1][3]);
+                    apq = (t[2][0] + t[2][1]) + (t[2][2] + t[2][3]);
+                }
+                bool act = lane < NP;
+                if (act && !finite3(app, aqq, apq)) {
+                    bad = 1;
+                    act = false;
+                }
+                act = act && needs_rotation(app, aqq, apq, a.tol);
+                const bool same = act ? (JP[pq.x] == JP[pq.y]) : true;
+                double c = 1.0, sn = 0.0;
+                if (act && transform_params(app, aqq, apq, same, c, sn) && wave == 0) ++ncl;
+                if (act) {
+                    double *yp = A + pq.x * P + r0w, *yq = A + pq.y * P + r0w;
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) {
+                        double x = yp[r], y = yq[r];
                         rotate_elems(x, y, c, sn, same);
-                        xp[r] = x;
-                        xq[r] = y;
+                        yp[r] = x;
+                        yq[r] = y;
                     }
-                    if (vbase) {
-                        double *yp = vbase + (size_t)pivot_col(pq.x, IJ, b) * a.ldv;
-                        double *yq = vbase + (size_t)pivot_col(pq.y, IJ, b) * a.ldv;
-                        for (int r = lane; r < a.nv; r += 64) {
-                            double x = yp[r], y = yq[r];
-                            rotate_elems(x, y, c, sn, same);
-                            yp[r] = x;
-                            yq[r] = y;
-                        }
+                    double *vp = VP + pq.x * P + r0w, *vq = VP + pq.y * P + r0w;
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) {
+                        double x = vp[r], y = vq[r];
+                        rotate_elems(x, y, c, sn, same);
+                        vp[r] = x;
+                        vq[r] = y;
                     }
-                    if (lane == 0) ++rot;
+                    if (wave == 0) ++rot_it;
                 }
                 __syncthreads();
             }
+        } else {
+            // G_P (and V) are transformed in place; there is no V_P to apply
+            inner_sweep_global<NW>(a.G, a.ldg, a.m, a.V, a.ldv, a.nv, JP, a.all_pairs, W, a.tol, IJ,
+                                   b, rot_it, ncl, &bad);
         }
+        rot += rot_it;
         // rotations of this inner sweep, summed over the workgroup
-        if (lane == 0) s_rot[wave] = rot - r0;
+        const double dr = (double)rot_it;
+        const double wr = wave_sum(dr);
+        if (lane == 0) s_rot[wave] = (unsigned long long)wr;
         __syncthreads();
         unsigned long long tot = 0;
         for (int w = 0; w < NW; ++w) tot += s_rot[w];
         __syncthreads();
         if (tot == 0) break;
     }
-    if (lane == 0) {
-        s_rot[wave] = rot;
-        s_cl[wave] = ncl;
+    {
+        const double wr = wave_sum((double)rot), wc = wave_sum((double)ncl);
+        if (lane == 0) {
+            s_rot[wave] = (unsigned long long)wr;
+            s_cl[wave] = (unsigned long long)wc;
+        }
     }
     if (bad) s_bad = 1;
     __syncthreads();
@@ -361,25 +481,30 @@ __global__ __launch_bounds__(1024) void k_pivot_solve(PivotSolveArgs a)
         if (tot) atomicAdd(&a.ctr->rotations, tot);
         if (totc) atomicAdd(&a.ctr->clamps, totc);
         if (broke) atomicAdd(&a.ctr->breakdowns, 1ull);
-        if (s_bad) atomicOr(&a.ctr->nonfinite, 1u);
+        if (s_bad) a.ctr->nonfinite = 1u;
         a.flag[pv] = (!broke && tot > 0 && !s_bad) ? 1 : 0;
     }
     if (!broke && tot > 0) {
         double *out = a.vpt + (size_t)pv * W * W;
-        for (int e = tid; e < W * W; e += 1024) {
+        for (int e = tid; e < W * W; e += kPivotThreads) {
             const int r = e / W, c = e % W;
-            out[e] = VP[c * W + r];
+            out[e] = VP[c * P + r];
         }
     }
 }
 
 // ---------------------------------------------------------------- k_update
+// One workgroup handles TILES consecutive 64-row tiles of one pivot (of G,
+// or of V): V_P is staged in LDS once, and the loads of tile t+1 are in
+// flight while the MFMAs of tile t run.
+constexpr int kUpdateTiles = 4;
+
 template <int W>
 __global__ __launch_bounds__(256) void k_update(double *__restrict__ G, int m, long ldg,
                                                 double *__restrict__ V, int nv, long ldv, int b,
                                                 const int2 *__restrict__ piv,
                                                 const double *__restrict__ vpt,
-                                                const int *__restrict__ flag, int tiles_g)
+                                                const int *__restrict__ flag, int groups_g)
 {
     constexpr int KS = W / 4;   // k-steps of the MFMA
     constexpr int NT = W / 16;  // output column tiles
@@ -387,39 +512,58 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ G, int m, l
     const int pv = blockIdx.y;
     if (flag[pv] != 1) return;
     const int2 IJ = piv[pv];
-    const bool isV = (int)blockIdx.x >= tiles_g;
+    const bool isV = (int)blockIdx.x >= groups_g;
     double *X = isV ? V : G;
     const long ld = isV ? ldv : ldg;
     const int rows = isV ? nv : m;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row = ((isV ? (int)blockIdx.x - tiles_g : (int)blockIdx.x) * 64) + wave * 16 + lane % 16;
+    const int group = isV ? (int)blockIdx.x - groups_g : (int)blockIdx.x;
+    const int row0 = group * 64 * kUpdateTiles + wave * 16 + lane % 16;
 
     const double *src = vpt + (size_t)pv * W * W;
     for (int e = threadIdx.x; e < W * W; e += 256) S[e] = src[e];
+    // Pivot columns 4g .. 4g+3 lie in one block (b is a multiple of 4), so
+    // the column of lane l in k-step ks is the wave-uniform pivot_col(4 ks)
+    // plus l / 16: wave-uniform column bases and one 32-bit per-lane offset.
+    const unsigned lane_off = (unsigned)(lane / 16) * (unsigned)ld;
     double bf[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        const int k = 4 * ks + lane / 16;
-        bf[ks] = (row < rows) ? X[(size_t)pivot_col(k, IJ, b) * ld + row] : 0.0;
+        const double *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
+        bf[ks] = (row0 < rows) ? cb[lane_off + (unsigned)row0] : 0.0;
     }
     __syncthreads();
-    d4 acc[NT];
+    for (int t = 0; t < kUpdateTiles; ++t) {
+        const int row = row0 + t * 64;
+        if (row - lane % 16 >= rows) break;   // the same for all lanes of the wavefront
+        double nb[KS];
+        const int rn = row + 64;
+        const bool more = t + 1 < kUpdateTiles && rn < rows;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < KS; ++ks) {
+            const double *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
+            nb[ks] = more ? cb[lane_off + (unsigned)rn] : 0.0;
+        }
+        d4 acc[NT];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const double *srow = S + (4 * ks + lane / 16) * W + (lane % 16);
+        for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = mfma16x16x4(srow[t * 16], bf[ks], acc[t]);
-    }
-    if (row < rows) {
+        for (int ks = 0; ks < KS; ++ks) {
+            const double *srow = S + (4 * ks + lane / 16) * W + (lane % 16);
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+            for (int q = 0; q < NT; ++q) acc[q] = mfma16x16x4(srow[q * 16], bf[ks], acc[q]);
+        }
+        if (row < rows) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int col = t * 16 + lane / 16 + 4 * r;
-                X[(size_t)pivot_col(col, IJ, b) * ld + row] = acc[t][r];
-            }
+            for (int q = 0; q < NT; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double *cb = X + (size_t)pivot_col(q * 16 + 4 * r, IJ, b) * ld;
+                    cb[lane_off + (unsigned)row] = acc[q][r];
+                }
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) bf[ks] = nb[ks];
     }
 }
 
@@ -473,13 +617,9 @@ int grow(T **p, size_t *cap, size_t need)
 
 struct BlockTables {
     int b = -1, N = -1;
-    std::vector<int> outer_start;
-    int2 *d_outer = nullptr;
+    std::vector<int> outer_start;   // host copy of the block ordering's step offsets
+    int2 *d_outer = nullptr;        // block pairs of every step (ring order)
     size_t cap_outer = 0;
-    int2 *d_inner = nullptr;      // full table, then cross table
-    int *d_inner_start = nullptr; // full starts, then cross starts
-    size_t cap_inner = 0, cap_inner_start = 0;
-    int nfull = 0, ncross = 0, full_pairs = 0;
 };
 
 static BlockTables *tables_of(BlockWorkspace *ws)
@@ -492,42 +632,21 @@ static int prepare_tables(BlockWorkspace *ws, int N, int b, hipStream_t st)
 {
     BlockTables *t = tables_of(ws);
     if (t->N == N && t->b == b) return JEVD_OK;
-    std::vector<int> os, op, fs, fp;
+    std::vector<int> os, op;
     build_ordering(N, kOrdModModulus, os, op);
-    const int W = 2 * b;
-    build_ordering(W, kOrdModModulus, fs, fp);
-    // cross pairs: step s = 0..b-1 holds (k, b + (k + s) mod b), k = 0..b-1
-    std::vector<int> cs, cp;
-    for (int s = 0; s < b; ++s) {
-        cs.push_back((int)cp.size() / 2);
-        for (int k = 0; k < b; ++k) {
-            cp.push_back(k);
-            cp.push_back(b + (k + s) % b);
-        }
-    }
-    cs.push_back((int)cp.size() / 2);
     int rc = grow(&t->d_outer, &t->cap_outer, op.size() / 2 + 1);
     if (rc) return rc;
-    std::vector<int> pairs(fp);
-    pairs.insert(pairs.end(), cp.begin(), cp.end());
-    std::vector<int> starts(fs);
-    for (int x : cs) starts.push_back(x + (int)fp.size() / 2);
-    rc = grow(&t->d_inner, &t->cap_inner, pairs.size() / 2 + 1);
-    if (rc) return rc;
-    rc = grow(&t->d_inner_start, &t->cap_inner_start, starts.size());
-    if (rc) return rc;
     HIP_TRY(hipMemcpyAsync(t->d_outer, op.data(), op.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(t->d_inner, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(t->d_inner_start, starts.data(), starts.size() * sizeof(int),
-                           hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     t->outer_start = os;
-    t->nfull = (int)fs.size() - 1;
-    t->ncross = (int)cs.size() - 1;
-    t->full_pairs = (int)fp.size() / 2;
     t->N = N;
     t->b = b;
     return JEVD_OK;
+}
+
+static size_t pivot_lds_bytes(int W)
+{
+    return (2 * (size_t)W * (W + 1) + 3 * (size_t)(kPivotThreads / 64) * (W / 2)) * sizeof(double);
 }
 
 template <int W>
@@ -554,9 +673,6 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     p.all_pairs = (a.full_block || k == 0) ? 1 : 0;
     p.full_block = a.full_block ? 1 : 0;
     p.max_inner = a.max_inner;
-    p.full = InnerTables{t->d_inner, t->d_inner_start, t->nfull};
-    // the cross starts follow the nfull + 1 offsets of the full table
-    p.cross = InnerTables{t->d_inner, t->d_inner_start + t->nfull + 1, t->ncross};
     p.vpt = ws->vp;
     p.flag = ws->flags;
     p.ctr = ctr;
@@ -566,18 +682,19 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     p.V = a.V;
     p.nv = a.n;
     p.ldv = a.ldv;
-    const size_t lds = 2 * (size_t)W * W * sizeof(double);
+    const size_t lds = pivot_lds_bytes(W);
     if ((e = a.timer->begin(st, JEVD_K_PIVOT_SOLVE)) != hipSuccess) return e;
-    k_pivot_solve<W><<<npiv, 1024, lds, st>>>(p);
+    k_pivot_solve<W><<<npiv, kPivotThreads, lds, st>>>(p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = a.timer->end(st)) != hipSuccess) return e;
 
-    const int tiles_g = (a.m + 63) / 64;
-    const int tiles_v = a.V ? (a.n + 63) / 64 : 0;
+    const int rows_per_group = 64 * kUpdateTiles;
+    const int groups_g = (a.m + rows_per_group - 1) / rows_per_group;
+    const int groups_v = a.V ? (a.n + rows_per_group - 1) / rows_per_group : 0;
     if ((e = a.timer->begin(st, JEVD_K_UPDATE)) != hipSuccess) return e;
-    k_update<W><<<dim3(tiles_g + tiles_v, npiv), 256, 0, st>>>(a.G, a.m, (long)a.ldg, a.V, a.n,
-                                                               (long)a.ldv, a.b, piv, ws->vp,
-                                                               ws->flags, tiles_g);
+    k_update<W><<<dim3(groups_g + groups_v, npiv), 256, 0, st>>>(a.G, a.m, (long)a.ldg, a.V, a.n,
+                                                                 (long)a.ldv, a.b, piv, ws->vp,
+                                                                 ws->flags, groups_g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return a.timer->end(st);
 }
@@ -590,8 +707,8 @@ int run_block(BlockWorkspace *ws, const BlockRunArgs &a, int *sweeps_done)
     int rc = prepare_tables(ws, N, b, a.stream);
     if (rc) return rc;
     BlockTables *t = tables_of(ws);
-    // split the rows of each Gram so that a step has about 2048 workgroups
-    int nsplit = 2048 / npiv;
+    // split the rows of each Gram so that a step has about 1024 workgroups
+    int nsplit = 1024 / npiv;
     if (nsplit < 1) nsplit = 1;
     int maxsplit = (a.m + 255) / 256;
     if (nsplit > maxsplit) nsplit = maxsplit;
@@ -604,10 +721,10 @@ int run_block(BlockWorkspace *ws, const BlockRunArgs &a, int *sweeps_done)
     if (rc) return rc;
     rc = grow(&ws->flags, &ws->capFlags, (size_t)npiv);
     if (rc) return rc;
-    if (W == 64 && 2 * (size_t)W * W * sizeof(double) > 65536)
+    if (W == 64)
         HIP_TRY(hipFuncSetAttribute((const void *)k_pivot_solve<64>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(2 * W * W * sizeof(double))));
+                                    (int)pivot_lds_bytes(64)));
     HIP_TRY(hipMemsetAsync(a.dctr, 0, sizeof(SweepCounters) * a.max_sweeps, a.stream));
     for (int s = 0; s < a.max_sweeps; ++s) {
         for (int k = 0; k < N; ++k) {
@@ -634,8 +751,6 @@ void block_workspace_free(BlockWorkspace *ws)
     if (ws->tables) {
         BlockTables *t = (BlockTables *)ws->tables;
         if (t->d_outer) (void)hipFree(t->d_outer);
-        if (t->d_inner) (void)hipFree(t->d_inner);
-        if (t->d_inner_start) (void)hipFree(t->d_inner_start);
         delete t;
     }
     *ws = BlockWorkspace();

@@ -110,18 +110,12 @@ int build_ordering(int n, int ordering, std::vector<int> &step_start, std::vecto
     }
     for (int k = 1; k <= N; ++k) {
         step_start.push_back((int)pairs.size() / 2);
-        for (int i = 1; i <= (k - 1) / 2; ++i) {          // antidiagonal i + j = k
-            pairs.push_back(i - 1);
-            pairs.push_back(k - i - 1);
-        }
-        const int hi = (k + N + 1) / 2 - 1;               // ceil((k+N)/2) - 1
-        for (int i = k; i <= hi; ++i) {                    // antidiagonal i + j = k + N
-            pairs.push_back(i - 1);
-            pairs.push_back(k + N - i - 1);
-        }
-        if (ordering == kOrdModModulus && N % 2 == 0 && k % 2 == 0) {
-            pairs.push_back(k / 2 - 1);
-            pairs.push_back(k / 2 + N / 2 - 1);
+        const int np = modulus_step_pairs(N, k, ordering == kOrdModModulus);
+        for (int r = 0; r < np; ++r) {
+            int i, j;
+            modulus_pair(N, k, r, &i, &j);
+            pairs.push_back(i);
+            pairs.push_back(j);
         }
     }
     step_start.push_back((int)pairs.size() / 2);

