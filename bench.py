@@ -196,6 +196,7 @@ def main():
                               "average includes dispatch gaps"}
     if block and kl[3]:
         npiv = N // 2
+        # one update launch transforms G (m rows) and V (n rows) of all pivots
         flops_update = npiv * (2.0 * b) ** 2 * 2.0 * (m + n)
         avg_ms = kms[3] / kl[3]
         achieved = flops_update / (avg_ms * 1e-3) / 1e12

@@ -13,7 +13,8 @@
 //                 inner one-sided sweeps on the columns of R (trig or
 //                 hyperbolic by J_P), accumulating V_P; writes V_P
 //                 row-major.  After a Cholesky breakdown the inner sweeps run
-//                 on the columns of G_P (and V) in place instead.
+//                 on the columns of G_P in place instead, still accumulating
+//                 V_P, which is then applied to V only.
 //   k_update      [G_I G_J] <- [G_I G_J] V_P and [V_I V_J] <- [V_I V_J] V_P
 //                 on FP64 MFMA, in place, 64 rows per workgroup: each
 //                 wavefront computes (G_P V_P)^T for 16 rows, so that both the
@@ -159,8 +160,9 @@ __device__ __forceinline__ int2 inner_pair(int all_pairs, int W, int s, int r)
 }
 
 // Breakdown path: one inner sweep directly on the columns of G_P (len rows,
-// pivot-local column k at X + pivot_col(k) * ldx) and of V, one wavefront per
-// pair, lanes over rows.  rot / ncl count on lane 0 of each wavefront.
+// pivot-local column k at X + pivot_col(k) * ldx), one wavefront per pair,
+// lanes over rows; the transforms are accumulated in V_P (Y: W x W, pitch
+// ldy), which is later applied to V only.  rot / ncl count on lane 0.
 template <int NW>
 __device__ void inner_sweep_global(double *X, long ldx, int len, double *Y, long ldy, int ylen,
                                    const signed char *JP, int all_pairs, int W, double tol,
@@ -198,9 +200,9 @@ __device__ void inner_sweep_global(double *X, long ldx, int len, double *Y, long
                 xp[r] = x;
                 xq[r] = y;
             }
-            if (Y) {
-                double *yp = Y + (size_t)pivot_col(pq.x, IJ, b) * ldy;
-                double *yq = Y + (size_t)pivot_col(pq.y, IJ, b) * ldy;
+            {
+                double *yp = Y + (size_t)pq.x * ldy;
+                double *yq = Y + (size_t)pq.y * ldy;
                 for (int r = lane; r < ylen; r += 64) {
                     double x = yp[r], y = yq[r];
                     rotate_elems(x, y, c, sn, same);
@@ -223,15 +225,13 @@ struct PivotSolveArgs {
     double tol;
     int all_pairs, full_block, max_inner;
     double *vpt;  // per pivot W x W, V_P row-major
-    int *flag;    // per pivot: 1 apply V_P, 0 nothing to apply
+    int *flag;    // per pivot: 1 apply V_P to G and V, 2 to V only (G_P was
+                  // transformed in place after a Cholesky breakdown), 0 none
     SweepCounters *ctr;
-    // for the breakdown path: the matrices themselves
+    // for the breakdown path: G itself
     double *G;
     int m;
     long ldg;
-    double *V;
-    int nv;
-    long ldv;
 };
 
 // LDS pitch of the factor R: one more than W (bank spread when the lanes of
@@ -357,18 +357,18 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     unsigned long long rot = 0, ncl = 0;
     int bad = 0;
     if (!broke) {
-        // R (upper) from the VP buffer into A, then V_P := I
+        // R (upper) from the VP buffer into A
         for (int e = tid; e < W * W; e += kPivotThreads) {
             const int r = e % W, c = e / W;
             A[c * P + r] = (r <= c) ? VP[c * P + r] : 0.0;
         }
         __syncthreads();
-        for (int e = tid; e < W * W; e += kPivotThreads) {
-            const int r = e % W, c = e / W;
-            VP[c * P + r] = (r == c) ? 1.0 : 0.0;
-        }
-        __syncthreads();
     }
+    for (int e = tid; e < W * W; e += kPivotThreads) {   // V_P := I
+        const int r = e % W, c = e / W;
+        VP[c * P + r] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
     const int sweeps = a.full_block ? a.max_inner : 1;
     const int r0w = wave * RPW;
     for (int it = 0; it < sweeps; ++it) {
@@ -448,9 +448,9 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
                 __syncthreads();
             }
         } else {
-            // G_P (and V) are transformed in place; there is no V_P to apply
-            inner_sweep_global<NW>(a.G, a.ldg, a.m, a.V, a.ldv, a.nv, JP, a.all_pairs, W, a.tol, IJ,
-                                   b, rot_it, ncl, &bad);
+            // G_P is transformed in place; V_P collects the transforms for V
+            inner_sweep_global<NW>(a.G, a.ldg, a.m, VP, P, W, JP, a.all_pairs, W, a.tol, IJ, b,
+                                   rot_it, ncl, &bad);
         }
         rot += rot_it;
         // rotations of this inner sweep, summed over the workgroup
@@ -482,9 +482,9 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
         if (totc) atomicAdd(&a.ctr->clamps, totc);
         if (broke) atomicAdd(&a.ctr->breakdowns, 1ull);
         if (s_bad) a.ctr->nonfinite = 1u;
-        a.flag[pv] = (!broke && tot > 0 && !s_bad) ? 1 : 0;
+        a.flag[pv] = (tot > 0 && !s_bad) ? (broke ? 2 : 1) : 0;
     }
-    if (!broke && tot > 0) {
+    if (tot > 0) {
         double *out = a.vpt + (size_t)pv * W * W;
         for (int e = tid; e < W * W; e += kPivotThreads) {
             const int r = e / W, c = e % W;
@@ -508,20 +508,24 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ G, int m, l
 {
     constexpr int KS = W / 4;   // k-steps of the MFMA
     constexpr int NT = W / 16;  // output column tiles
-    __shared__ double S[W * W]; // V_P row-major
+    // V_P row-major with a row pitch of W + 16 doubles: the four 16-lane row
+    // groups of a fragment read then cover all 64 LDS banks in two cycles
+    constexpr int SP = W + 16;
+    __shared__ double S[W * SP];
     const int pv = blockIdx.y;
-    if (flag[pv] != 1) return;
+    const bool is_v = (int)blockIdx.x >= groups_g;
+    const int f = flag[pv];
+    if (!(f == 1 || (is_v && f == 2))) return;   // flag 2: G_P already transformed
+    double *X = is_v ? V : G;
+    const long ld = is_v ? ldv : ldg;
+    const int rows = is_v ? nv : m;
     const int2 IJ = piv[pv];
-    const bool isV = (int)blockIdx.x >= groups_g;
-    double *X = isV ? V : G;
-    const long ld = isV ? ldv : ldg;
-    const int rows = isV ? nv : m;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int group = isV ? (int)blockIdx.x - groups_g : (int)blockIdx.x;
+    const int group = is_v ? (int)blockIdx.x - groups_g : (int)blockIdx.x;
     const int row0 = group * 64 * kUpdateTiles + wave * 16 + lane % 16;
 
     const double *src = vpt + (size_t)pv * W * W;
-    for (int e = threadIdx.x; e < W * W; e += 256) S[e] = src[e];
+    for (int e = threadIdx.x; e < W * W; e += 256) S[(e / W) * SP + (e % W)] = src[e];
     // Pivot columns 4g .. 4g+3 lie in one block (b is a multiple of 4), so
     // the column of lane l in k-step ks is the wave-uniform pivot_col(4 ks)
     // plus l / 16: wave-uniform column bases and one 32-bit per-lane offset.
@@ -549,7 +553,7 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ G, int m, l
         for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const double *srow = S + (4 * ks + lane / 16) * W + (lane % 16);
+            const double *srow = S + (4 * ks + lane / 16) * SP + (lane % 16);
 #pragma unroll
             for (int q = 0; q < NT; ++q) acc[q] = mfma16x16x4(srow[q * 16], bf[ks], acc[q]);
         }
@@ -649,6 +653,7 @@ static size_t pivot_lds_bytes(int W)
     return (2 * (size_t)W * (W + 1) + 3 * (size_t)(kPivotThreads / 64) * (W / 2)) * sizeof(double);
 }
 
+// One outer step: Gram, pivot solve, update of G and V (one launch).
 template <int W>
 static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTables *t, int k,
                               int nsplit, int rows_per_split, SweepCounters *ctr)
@@ -679,12 +684,8 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     p.G = a.G;
     p.m = a.m;
     p.ldg = a.ldg;
-    p.V = a.V;
-    p.nv = a.n;
-    p.ldv = a.ldv;
-    const size_t lds = pivot_lds_bytes(W);
     if ((e = a.timer->begin(st, JEVD_K_PIVOT_SOLVE)) != hipSuccess) return e;
-    k_pivot_solve<W><<<npiv, kPivotThreads, lds, st>>>(p);
+    k_pivot_solve<W><<<npiv, kPivotThreads, pivot_lds_bytes(W), st>>>(p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = a.timer->end(st)) != hipSuccess) return e;
 

@@ -130,6 +130,30 @@ def test_block_workload_recipe_small(solver, orc):
     print("n=1024 block workload recipe: sweeps gpu %d oracle %d" % (got["sweeps"], ref.sweeps))
 
 
+@pytest.mark.parametrize("full_block", [False, True])
+def test_block_cholesky_breakdown_path(solver, orc, full_block):
+    """A zero column gives a pivot Gram a zero diagonal entry, so its Cholesky
+    factorisation breaks down on both sides (deterministically); that pivot
+    is then processed on the columns of G_P itself, with V_P still
+    accumulated for V."""
+    n = 128
+    G = W.graded_rows(n + 8, n, k=77, decades=2.0, cond_decades=2.0)
+    G[:, 37] = 0.0
+    got = run(solver, G, None, n * EPS, 2 if full_block else 1, 32)
+    ref = orc.block_jevd(G, None, n * EPS, b=32, full_block=full_block, want_v=True)
+    assert ref.extra > 0 and got["info"].breakdowns > 0
+    assert ref.status == 0 and got["st"] == 0
+    assert got["lam"][37] == 0.0 and np.all(got["U"][:, 37] == 0.0)
+    nz = np.arange(n) != 37
+    assert rel_err(got["lam"][nz], ref.lam[nz]) <= REL_TOL
+    V = got["V"]
+    assert np.max(np.abs(V.T @ V - np.eye(n))) <= max(10 * n * EPS, 4 * np.max(np.abs(ref.V.T @ ref.V - np.eye(n))))
+    GV = (G.astype(np.longdouble) @ V.astype(np.longdouble)).astype(np.float64)
+    scale = np.sqrt(np.sum((np.abs(G) @ np.abs(V)) ** 2, axis=0))
+    scale[scale == 0] = 1.0
+    assert np.max(np.abs(GV - got["G"]).sum(axis=0) / scale) <= 100 * n * EPS
+
+
 def test_block_status_paths(solver, orc):
     G = W.graded_rows(128, 128, k=9, decades=2.0)
     got = run(solver, G, None, 0.0, 1, 32, max_sweeps=1)
