@@ -137,6 +137,50 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
                double tol, const jevd_opts *opts, double *lambda, double *U, int ldu,
                double *V, int ldv, int *sweeps);
 
+/*
+ * Batched solves: many independent instances H_i = G_i J_i G_i^T, each
+ * treated exactly as jacobi_evd treats one (pointwise sweeps, the ordering,
+ * tolerance and sweep limit of opts), in one persistent launch (Sec. 2.4:
+ * instances, like disjoint pivots, are independent).  Meant for many small
+ * and medium problems (n up to a few hundred).
+ *
+ * jevd_batch_create validates every instance (the rules of jacobi_evd;
+ * JEVD_EINVAL before any device work), copies the J_i to the device and
+ * uploads one descriptor per instance, queued largest first.  All pointer
+ * arrays are HOST arrays of length batch: G, lambda, U, V hold DEVICE
+ * pointers (lambda, U, V arrays or entries may be NULL), J holds HOST
+ * pointers to n_i signs (J or an entry NULL: J = I), tol holds per-instance
+ * tolerances (NULL or an entry <= 0: n_i * DBL_EPSILON).  opts->variant must
+ * be JEVD_VAR_POINTWISE or JEVD_VAR_AUTO.  The plan refers to the caller's
+ * buffers; they must stay valid while it is run.
+ * jevd_batch_run enqueues the solve of all instances on `stream` (a
+ * hipStream_t; NULL: the handle's stream) and returns at once: it launches
+ * two kernels and nothing else, so it may be captured in a HIP graph and
+ * replayed.  Each run restarts from the current contents of the G_i.
+ * jevd_batch_results waits for the stream of the last run and copies out
+ * the per-instance sweep counts and statuses (JEVD_OK, JEVD_ENOCONV,
+ * JEVD_ENONFINITE); either array may be NULL.  It returns JEVD_OK if every
+ * instance converged, else the first failing instance's status.
+ * Plans of one handle may not run concurrently.
+ */
+typedef struct jevd_batch_s *jevd_batch_t;
+
+int jevd_batch_create(jevd_handle_t h, int batch, const int *m, const int *n,
+                      double *const *G, const int *ldg, const signed char *const *J,
+                      const double *tol, const jevd_opts *opts, double *const *lambda,
+                      double *const *U, const int *ldu, double *const *V, const int *ldv,
+                      jevd_batch_t *plan);
+int jevd_batch_run(jevd_batch_t plan, void *stream);
+int jevd_batch_results(jevd_batch_t plan, int *sweeps, int *status);
+int jevd_batch_destroy(jevd_batch_t plan);
+
+/* create + run on the handle's stream + results + destroy. */
+int jacobi_evd_batched(jevd_handle_t h, int batch, const int *m, const int *n,
+                       double *const *G, const int *ldg, const signed char *const *J,
+                       const double *tol, const jevd_opts *opts, double *const *lambda,
+                       double *const *U, const int *ldu, double *const *V, const int *ldv,
+                       int *sweeps, int *status);
+
 /* Host-only argument check that jacobi_evd runs before any device work
  * (same rules; G, lambda and the handle are not examined).  Returns JEVD_OK
  * or JEVD_EINVAL.  No device work. */

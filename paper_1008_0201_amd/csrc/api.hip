@@ -1,10 +1,12 @@
 // C ABI of the one-sided Jacobi solver (include/jevd.h): argument checks,
 // workspace, the sweep loop and the dispatch to the pointwise and block
 // kernels.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -15,6 +17,33 @@
 #include "ordering.h"
 
 using namespace jevd;
+
+namespace jevd {
+struct BatchInst {  // mirrors the device-side descriptor in batched.hip
+    double *G;
+    double *V;
+    double *lambda;
+    double *U;
+    const signed char *J;
+    double tol;
+    int m, n, ldg, ldv, ldu;
+};
+}  // namespace jevd
+
+struct jevd_batch_s {
+    jevd_handle_t h = nullptr;
+    int batch = 0;
+    int ordering = 0, max_sweeps = 50, accumulate_v = 0;
+    int grid = 0;
+    BatchInst *d_inst = nullptr;
+    int *d_order = nullptr;
+    int *d_queue = nullptr;
+    int *d_sweeps = nullptr;   // per instance
+    int *d_status = nullptr;   // per instance
+    signed char *d_J = nullptr;
+    hipStream_t last = nullptr;
+    bool ran = false;
+};
 
 struct jevd_handle_s {
     int device = 0;
@@ -359,6 +388,148 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
     }
     if (sweeps) *sweeps = sweeps_done;
     return status;
+}
+
+int jevd_batch_destroy(jevd_batch_t p)
+{
+    if (!p) return JEVD_OK;
+    if (p->ran) (void)hipStreamSynchronize(p->last);
+    if (p->d_inst) (void)hipFree(p->d_inst);
+    if (p->d_order) (void)hipFree(p->d_order);
+    if (p->d_queue) (void)hipFree(p->d_queue);
+    if (p->d_sweeps) (void)hipFree(p->d_sweeps);
+    if (p->d_status) (void)hipFree(p->d_status);
+    if (p->d_J) (void)hipFree(p->d_J);
+    delete p;
+    return JEVD_OK;
+}
+
+int jevd_batch_create(jevd_handle_t h, int batch, const int *m, const int *n, double *const *G,
+                      const int *ldg, const signed char *const *J, const double *tol,
+                      const jevd_opts *opts, double *const *lambda, double *const *U,
+                      const int *ldu, double *const *V, const int *ldv, jevd_batch_t *plan)
+{
+    if (!plan) return JEVD_EINVAL;
+    *plan = nullptr;
+    if (!h || batch < 1 || !m || !n || !G || !ldg) return JEVD_EINVAL;
+    jevd_opts o;
+    fill_defaults(&o);
+    if (opts) o = *opts;
+    if (o.variant != JEVD_VAR_POINTWISE && o.variant != JEVD_VAR_AUTO) return JEVD_EINVAL;
+    std::vector<BatchInst> hi(batch);
+    size_t jtotal = 0;
+    for (int i = 0; i < batch; ++i) {
+        const double *Ui = U ? U[i] : nullptr;
+        const double *Vi = V ? V[i] : nullptr;
+        const double ti = tol ? tol[i] : 0.0;
+        const int st = jevd_validate(m[i], n[i], ldg[i], J ? J[i] : nullptr, ti, &o, Ui,
+                                     Ui ? ldu[i] : m[i], Vi, Vi ? ldv[i] : n[i]);
+        if (st) return st;
+        if (!G[i]) return JEVD_EINVAL;
+        if (J && J[i]) jtotal += (size_t)n[i];
+    }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != h->device) return JEVD_EINVAL;
+    HIP_TRY(prepare_batch_kernel());
+    jevd_batch_s *p = new (std::nothrow) jevd_batch_s();
+    if (!p) return JEVD_ENOMEM;
+    p->h = h;
+    p->batch = batch;
+    p->ordering = o.ordering;
+    p->max_sweeps = o.max_sweeps;
+    p->accumulate_v = o.accumulate_v;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    p->grid = std::min(batch, cus);   // one persistent workgroup per CU (it takes all of LDS)
+    std::vector<signed char> hJ(jtotal > 0 ? jtotal : 1);
+    std::vector<size_t> joff(batch, (size_t)-1);
+    size_t off = 0;
+    for (int i = 0; i < batch; ++i)
+        if (J && J[i]) {
+            std::memcpy(hJ.data() + off, J[i], (size_t)n[i]);
+            joff[i] = off;
+            off += (size_t)n[i];
+        }
+    auto fail = [&](hipError_t e) {
+        (void)hipGetLastError();
+        jevd_batch_destroy(p);
+        return e == hipErrorOutOfMemory ? JEVD_ENOMEM : JEVD_EHIP;
+    };
+    hipError_t e;
+    if ((e = hipMalloc((void **)&p->d_inst, sizeof(BatchInst) * batch)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc((void **)&p->d_order, sizeof(int) * batch)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc((void **)&p->d_queue, sizeof(int))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc((void **)&p->d_sweeps, sizeof(int) * batch)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc((void **)&p->d_status, sizeof(int) * batch)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc((void **)&p->d_J, hJ.size())) != hipSuccess) return fail(e);
+    for (int i = 0; i < batch; ++i) {
+        BatchInst &d = hi[i];
+        d.G = G[i];
+        d.V = V ? V[i] : nullptr;
+        d.lambda = lambda ? lambda[i] : nullptr;
+        d.U = U ? U[i] : nullptr;
+        d.J = (joff[i] != (size_t)-1) ? p->d_J + joff[i] : nullptr;
+        d.tol = (tol && tol[i] > 0) ? tol[i] : n[i] * DBL_EPSILON;
+        d.m = m[i];
+        d.n = n[i];
+        d.ldg = ldg[i];
+        d.ldv = d.V ? ldv[i] : n[i];
+        d.ldu = d.U ? ldu[i] : m[i];
+    }
+    // longest processing time first: about n^2 m work per sweep
+    std::vector<int> order(batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (double)n[a] * n[a] * m[a] > (double)n[b] * n[b] * m[b];
+    });
+    if ((e = hipMemcpy(p->d_inst, hi.data(), sizeof(BatchInst) * batch, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemcpy(p->d_order, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    if ((e = hipMemcpy(p->d_J, hJ.data(), hJ.size(), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+    *plan = p;
+    return JEVD_OK;
+}
+
+int jevd_batch_run(jevd_batch_t p, void *stream)
+{
+    if (!p) return JEVD_EINVAL;
+    hipStream_t st = stream ? (hipStream_t)stream : p->h->stream;
+    HIP_TRY(launch_batch(p->d_inst, p->d_order, p->batch, p->d_queue, p->ordering, p->max_sweeps,
+                         p->accumulate_v, p->d_sweeps, p->d_status, p->grid, st));
+    p->last = st;
+    p->ran = true;
+    return JEVD_OK;
+}
+
+int jevd_batch_results(jevd_batch_t p, int *sweeps, int *status)
+{
+    if (!p || !p->ran) return JEVD_EINVAL;
+    HIP_TRY(hipStreamSynchronize(p->last));
+    std::vector<int> sw(p->batch), stv(p->batch);
+    HIP_TRY(hipMemcpy(sw.data(), p->d_sweeps, sizeof(int) * p->batch, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(stv.data(), p->d_status, sizeof(int) * p->batch, hipMemcpyDeviceToHost));
+    if (sweeps) std::memcpy(sweeps, sw.data(), sizeof(int) * p->batch);
+    if (status) std::memcpy(status, stv.data(), sizeof(int) * p->batch);
+    for (int i = 0; i < p->batch; ++i)
+        if (stv[i] != JEVD_OK) return stv[i];
+    return JEVD_OK;
+}
+
+int jacobi_evd_batched(jevd_handle_t h, int batch, const int *m, const int *n, double *const *G,
+                       const int *ldg, const signed char *const *J, const double *tol,
+                       const jevd_opts *opts, double *const *lambda, double *const *U,
+                       const int *ldu, double *const *V, const int *ldv, int *sweeps, int *status)
+{
+    jevd_batch_t p = nullptr;
+    int st = jevd_batch_create(h, batch, m, n, G, ldg, J, tol, opts, lambda, U, ldu, V, ldv, &p);
+    if (st) return st;
+    st = jevd_batch_run(p, nullptr);
+    if (st == JEVD_OK) st = jevd_batch_results(p, sweeps, status);
+    jevd_batch_destroy(p);
+    return st;
 }
 
 }  // extern "C"

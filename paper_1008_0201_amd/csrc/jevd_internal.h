@@ -132,6 +132,12 @@ struct KernelTimer {
 };
 
 hipError_t launch_pair_step(const PairStepArgs &a, hipStream_t st);
+
+struct BatchInst;
+hipError_t prepare_batch_kernel();  // once before the first launch (sets the LDS limit)
+hipError_t launch_batch(const BatchInst *inst, const int *order, int batch, int *queue,
+                        int ordering, int max_sweeps, int accumulate_v, int *sweeps, int *status,
+                        int grid, hipStream_t st);
 hipError_t launch_small_solve(const SmallSolveArgs &a, hipStream_t st);
 hipError_t launch_sum_slots(unsigned *slot_rot, unsigned *slot_clamp, int nslots,
                             SweepCounters *ctr, hipStream_t st);

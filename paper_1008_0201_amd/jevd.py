@@ -17,7 +17,9 @@ VAR_POINTWISE, VAR_BLOCK_ORIENTED, VAR_FULL_BLOCK, VAR_AUTO = 0, 1, 2, 3
 INFO_MAX_SWEEPS = 64
 
 EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "jevd_validate",
-           "jevd_get_info", "jevd_set_timing", "jevd_strerror", "jevd_ordering")
+           "jevd_get_info", "jevd_set_timing", "jevd_strerror", "jevd_ordering",
+           "jevd_batch_create", "jevd_batch_run", "jevd_batch_results", "jevd_batch_destroy",
+           "jacobi_evd_batched")
 K_PAIR_STEP, K_GRAM, K_PIVOT_SOLVE, K_UPDATE = 0, 1, 2, 3
 
 
@@ -66,6 +68,13 @@ def lib():
         L.jevd_strerror.argtypes = [ctypes.c_int]
         L.jevd_strerror.restype = ctypes.c_char_p
         L.jevd_ordering.argtypes = [ctypes.c_int, ctypes.c_int, _ip, _ip, _ip, _ip]
+        batch_args = [_vp, ctypes.c_int, _ip, _ip, _vp, _ip, _vp, _vp, ctypes.POINTER(jevd_opts),
+                      _vp, _vp, _ip, _vp, _ip]
+        L.jevd_batch_create.argtypes = batch_args + [ctypes.POINTER(_vp)]
+        L.jevd_batch_run.argtypes = [_vp, _vp]
+        L.jevd_batch_results.argtypes = [_vp, _ip, _ip]
+        L.jevd_batch_destroy.argtypes = [_vp]
+        L.jacobi_evd_batched.argtypes = batch_args + [_ip, _ip]
         for name in EXPORTS:
             if name != "jevd_strerror":
                 getattr(L, name).restype = ctypes.c_int
@@ -146,6 +155,71 @@ def jevd_ordering(n, ordering):
             for k in range(ns.value)]
 
 
+class _BatchArgs:
+    """Host arrays of one batch (lengths = batch), kept alive with the plan."""
+
+    def __init__(self, m, n, G_ptrs, ldg, J_list, tol, lam_ptrs, U_ptrs, ldu, V_ptrs, ldv):
+        b = len(m)
+        ia = ctypes.c_int * b
+        pa = _vp * b
+        self.batch = b
+        self.m, self.n, self.ldg = ia(*m), ia(*n), ia(*ldg)
+        self.G = pa(*[_vp(p) for p in G_ptrs])
+        self.Jbufs = []
+        self.J = None
+        if J_list is not None and any(j is not None for j in J_list):
+            self.J = pa()
+            for i, j in enumerate(J_list):
+                if j is not None:
+                    buf = (ctypes.c_byte * len(bytes(j))).from_buffer_copy(bytes(j))
+                    self.Jbufs.append(buf)
+                    self.J[i] = ctypes.cast(buf, _vp)
+        self.tol = None if tol is None else (ctypes.c_double * b)(*[float(t) for t in tol])
+
+        def ptrs(lst):
+            return None if lst is None else pa(*[_vp(p) if p else None for p in lst])
+
+        self.lam, self.U, self.V = ptrs(lam_ptrs), ptrs(U_ptrs), ptrs(V_ptrs)
+        self.ldu = None if ldu is None else ia(*ldu)
+        self.ldv = None if ldv is None else ia(*ldv)
+
+    def call_args(self, h, opts):
+        return (h, self.batch, self.m, self.n, self.G, self.ldg, self.J, self.tol,
+                ctypes.byref(opts) if opts is not None else None, self.lam, self.U, self.ldu,
+                self.V, self.ldv)
+
+
+def jevd_batch_create(h, m, n, G_ptrs, ldg, J_list, tol, opts, lam_ptrs, U_ptrs, ldu, V_ptrs, ldv):
+    """Raw plan creation: lists of ints (device pointers as ints, 0 = NULL),
+    J_list of bytes-like int8 or None.  Returns (status, plan, keepalive)."""
+    a = _BatchArgs(m, n, G_ptrs, ldg, J_list, tol, lam_ptrs, U_ptrs, ldu, V_ptrs, ldv)
+    plan = _vp()
+    st = lib().jevd_batch_create(*a.call_args(h, opts), ctypes.byref(plan))
+    return st, plan, a
+
+
+def jevd_batch_run(plan, stream=0):
+    return lib().jevd_batch_run(plan, _vp(int(stream)) if stream else None)
+
+
+def jevd_batch_results(plan, batch):
+    sw, stv = (ctypes.c_int * batch)(), (ctypes.c_int * batch)()
+    st = lib().jevd_batch_results(plan, sw, stv)
+    return st, list(sw), list(stv)
+
+
+def jevd_batch_destroy(plan):
+    return lib().jevd_batch_destroy(plan)
+
+
+def jacobi_evd_batched(h, m, n, G_ptrs, ldg, J_list, tol, opts, lam_ptrs, U_ptrs, ldu, V_ptrs, ldv):
+    """Returns (status, sweeps list, status list)."""
+    a = _BatchArgs(m, n, G_ptrs, ldg, J_list, tol, lam_ptrs, U_ptrs, ldu, V_ptrs, ldv)
+    sw, stv = (ctypes.c_int * a.batch)(), (ctypes.c_int * a.batch)()
+    st = lib().jacobi_evd_batched(*a.call_args(h, opts), sw, stv)
+    return st, list(sw), list(stv)
+
+
 # ----------------------------------------------------------- torch front end
 class Solver:
     """Owns a handle bound to the current device and torch's current stream."""
@@ -204,8 +278,86 @@ class Solver:
             raise JevdError(st, "jacobi_evd")
         return lam, U, V, sweeps, st
 
+    def batch_plan(self, Gs, Js=None, tols=None, ordering=ORD_MODMODULUS, max_sweeps=50,
+                   want_U=True, want_V=True):
+        """Plan for the device tensors Gs (float64, column-major, solved in
+        place).  Returns a BatchPlan holding lam/U/V output tensors."""
+        return BatchPlan(self, Gs, Js, tols, ordering, max_sweeps, want_U, want_V)
+
+    def evd_batched(self, Gs, Js=None, tols=None, ordering=ORD_MODMODULUS, max_sweeps=50,
+                    want_U=True, want_V=True, check=True):
+        """One batched solve.  Returns (lams, Us, Vs, sweeps, statuses)."""
+        plan = self.batch_plan(Gs, Js, tols, ordering, max_sweeps, want_U, want_V)
+        try:
+            plan.run()
+            st, sweeps, stv = plan.results()
+            if check and st != JEVD_OK:
+                raise JevdError(st, "jevd_batch_results")
+            return plan.lams, plan.Us, plan.Vs, sweeps, stv
+        finally:
+            plan.close()
+
     def info(self):
         return jevd_get_info(self.h)
 
     def set_timing(self, on):
         jevd_set_timing(self.h, on)
+
+
+class BatchPlan:
+    """A jevd_batch_t over torch device tensors (see Solver.batch_plan)."""
+
+    def __init__(self, solver, Gs, Js, tols, ordering, max_sweeps, want_U, want_V):
+        import torch
+        import numpy as np
+        self.solver = solver
+        self.plan = None
+        m, n, ldg, gp, Jl = [], [], [], [], []
+        self.lams, self.Us, self.Vs = [], [], []
+        for i, G in enumerate(Gs):
+            if G.dtype != torch.float64 or not G.is_cuda or G.stride(0) != 1:
+                raise TypeError("batch entry %d: G must be a column-major float64 device tensor" % i)
+            mi, ni = G.shape
+            m.append(mi)
+            n.append(ni)
+            ldg.append(G.stride(1) if ni > 1 else mi)
+            gp.append(G.data_ptr())
+            J = None if Js is None else Js[i]
+            Jl.append(None if J is None else
+                      np.ascontiguousarray(np.asarray(J.cpu() if hasattr(J, "cpu") else J)
+                                           .astype(np.int8)).tobytes())
+            self.lams.append(torch.empty(ni, dtype=torch.float64, device=G.device))
+            self.Us.append(torch.empty((ni, mi), dtype=torch.float64, device=G.device).T
+                           if want_U else None)
+            self.Vs.append(torch.empty((ni, ni), dtype=torch.float64, device=G.device).T
+                           if want_V else None)
+        o = jevd_default_opts()
+        o.ordering, o.variant, o.max_sweeps = ordering, VAR_POINTWISE, max_sweeps
+        st, plan, self._keep = jevd_batch_create(
+            solver.h, m, n, gp, ldg, Jl if Js is not None else None, tols, o,
+            [t.data_ptr() for t in self.lams],
+            [u.data_ptr() for u in self.Us] if want_U else None, m if want_U else None,
+            [v.data_ptr() for v in self.Vs] if want_V else None, n if want_V else None)
+        if st != JEVD_OK:
+            raise JevdError(st, "jevd_batch_create")
+        self.plan = plan
+        self.batch = len(m)
+
+    def run(self, stream=None):
+        st = jevd_batch_run(self.plan, stream.cuda_stream if stream is not None else 0)
+        if st != JEVD_OK:
+            raise JevdError(st, "jevd_batch_run")
+
+    def results(self):
+        return jevd_batch_results(self.plan, self.batch)
+
+    def close(self):
+        if self.plan:
+            jevd_batch_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

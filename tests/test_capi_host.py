@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports
 every function include/jevd.h declares, and its host logic (argument
 validation, orderings, defaults, messages) is right."""
+import ctypes
 import os
 import re
 
@@ -98,3 +99,21 @@ def test_ring_table_keeps_one_column_per_slot(n):
             assert len(shared) == 1, (k, b, steps[k][b], steps[k + 1][b])
     first = {tuple(sorted(pr)) for pr in steps[0]}
     assert first == {(r, n - 1 - r) for r in range(p)}
+
+
+def test_batch_entry_points_reject_null_arguments():
+    """The batched entry points check their handles and arrays on the host
+    before any device work (no GPU needed for these paths)."""
+    L = B.lib()
+    plan = ctypes.c_void_p(123)
+    m = (ctypes.c_int * 1)(4)
+    st = L.jevd_batch_create(None, 1, m, m, None, m, None, None, None, None, None, None, None,
+                             None, ctypes.byref(plan))
+    assert st == B.JEVD_EINVAL and plan.value is None
+    assert L.jevd_batch_create(None, 1, m, m, None, m, None, None, None, None, None, None, None,
+                               None, None) == B.JEVD_EINVAL
+    assert L.jevd_batch_run(None, None) == B.JEVD_EINVAL
+    assert L.jevd_batch_results(None, None, None) == B.JEVD_EINVAL
+    assert L.jevd_batch_destroy(None) == B.JEVD_OK
+    assert L.jacobi_evd_batched(None, 1, m, m, None, m, None, None, None, None, None, None, None,
+                                None, None, None) == B.JEVD_EINVAL
