@@ -44,7 +44,13 @@ def check_instance(orc, G, J, tol, ordering, lam, U, V, Gout, sweeps, st, tag):
     ref = orc.jevd(G, J, tol, ordering, want_v=False)
     assert ref.status == 0
     assert st == 0, (tag, st)
-    assert rel_err(lam, ref.lam) <= REL_TOL, tag
+    e = rel_err(lam, ref.lam)
+    if e > REL_TOL:
+        # the FP64 oracle itself can miss 1e-12 on an ill-conditioned
+        # instance: then both are judged against the 80-bit oracle
+        hi = orc.jevd(G, J, tol, ordering, want_v=False, prec="l")
+        e_gpu, e_ref = rel_err(lam, hi.lam), rel_err(ref.lam, hi.lam)
+        assert e_gpu <= max(REL_TOL, 4 * e_ref), (tag, e_gpu, e_ref)
     assert abs(sweeps - ref.sweeps) <= 1, (tag, sweeps, ref.sweeps)
     n = G.shape[1]
     if U is not None:
