@@ -28,8 +28,11 @@ nonzero eigenvalues):
 Hence <dL/dH, dH> = <X, dH> with
   X = U diag(w) U^T + U (F o U^T C) U^T + (I - U U^T) C Lambda^{-1} U^T,
   F_ki = 1 / (lambda_i - lambda_k) (k != i), F_ii = 0,
-and, pulled back through dH, dL/dG = (X + X^T) G J.  The functions below
-write these definitions out as they stand.
+and, pulled back through dH, dL/dG = (X + X^T) G J.  Two exact zeros are
+left out rather than formed: the transpose of the last term of X multiplies
+(I - U U^T) G, which vanishes because the columns of G lie in the range of U
+(full column rank), and for m = n that term is empty.  Formed in floating
+point they are rounding noise of size eps |G| / min |lambda_i|.
 """
 import numpy as np
 
@@ -78,5 +81,7 @@ def adjoint(G, J, lam, U, w=None, C=None):
                 if k != i:
                     F[k, i] = 1.0 / (lam[i] - lam[k])
         X += U @ (F * (U.T @ C)) @ U.T
-        X += (np.eye(m) - U @ U.T) @ C @ np.diag(1.0 / lam) @ U.T
-    return (X + X.T) @ G @ np.diag(Jd)
+    out = (X + X.T) @ G @ np.diag(Jd)
+    if C is not None and m > n:
+        out += (np.eye(m) - U @ U.T) @ C @ np.diag(1.0 / lam) @ U.T @ G @ np.diag(Jd)
+    return out

@@ -121,10 +121,11 @@ def test_invariances(orc, kind, m, n, seed):
 
 
 MUTANTS = {
-    "transpose-term-dropped": ("return (X + X.T) @ G @ np.diag(Jd)", "return 2 * X @ G @ np.diag(Jd)"),
+    "transpose-term-dropped": ("out = (X + X.T) @ G @ np.diag(Jd)", "out = 2 * X @ G @ np.diag(Jd)"),
     "gap-sign-flipped": ("F[k, i] = 1.0 / (lam[i] - lam[k])", "F[k, i] = 1.0 / (lam[k] - lam[i])"),
-    "complement-dropped": ("X += (np.eye(m) - U @ U.T) @ C @ np.diag(1.0 / lam) @ U.T", "pass"),
-    "signature-dropped": ("return (X + X.T) @ G @ np.diag(Jd)", "return (X + X.T) @ G"),
+    "complement-dropped": ("out += (np.eye(m) - U @ U.T) @ C @ np.diag(1.0 / lam) @ U.T @ G @ np.diag(Jd)",
+                           "pass"),
+    "signature-dropped": ("out = (X + X.T) @ G @ np.diag(Jd)", "out = (X + X.T) @ G"),
     "operands-transposed": ("X += U @ (F * (U.T @ C)) @ U.T", "X += U @ (F * (C.T @ U)) @ U.T"),
     "weights-halved": ("X += U @ np.diag(w) @ U.T", "X += 0.5 * U @ np.diag(w) @ U.T"),
 }
