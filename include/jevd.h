@@ -181,6 +181,46 @@ int jacobi_evd_batched(jevd_handle_t h, int batch, const int *m, const int *n,
                        double *const *U, const int *ldu, double *const *V, const int *ldv,
                        int *sweeps, int *status);
 
+/*
+ * Canonical outputs and the adjoint, for `batch` instances of one shape
+ * m x n (1 <= n <= m), stored column-major at fixed strides: instance b of
+ * an array X with leading dimension ldx and batch stride sx starts at
+ * X + b * sx (sx >= ldx * n; for lam, w: >= n).  All pointers are DEVICE
+ * pointers; both calls only enqueue work on the handle's stream (no
+ * synchronisation, no host transfers) and return JEVD_EINVAL on bad sizes,
+ * JEVD_ENOMEM / JEVD_EHIP on device errors.
+ *
+ * jevd_canonicalize: writes a canonical form of solver outputs (lam, U and
+ * optionally V, as left by jacobi_evd or a batch plan): eigenpairs sorted by
+ * decreasing lambda (equal values by position; NaN ordered as -inf), each
+ * u_i signed so that its entry of largest magnitude (the first such) is
+ * positive, v_i signed and moved with it.  The outputs use the same leading
+ * dimensions and strides and must not overlap the inputs.  The order and
+ * signs the iteration leaves depend on its rotation sequence; the canonical
+ * form makes (lam, U) a locally smooth function of G for a simple spectrum.
+ *
+ * jevd_adjoint: dG = dL/dG for L = sum_i w_i lambda_i + <C, U>, given the
+ * input G and J of H = G J G^T and the canonical lam, U of its solve (Sec. 1
+ * and Sec. 2.1; first-order perturbation theory of a symmetric matrix with
+ * a simple spectrum, pulled back through dH = dG J G^T + G J dG^T):
+ *   dG = [U M' + (m > n ? C Lambda^{-1} : 0)] W J,  W = U^T G,  K = U^T C,
+ *   M'_ki = (K_ki - K_ik) / (lambda_i - lambda_k)  (k != i),  M'_ii = 2 w_i,
+ *   and, if m > n, minus K_ki / lambda_i in every entry.
+ * J here is a DEVICE array of n int8 signs per instance (batch stride sj >=
+ * n), or NULL for J = I.  w or C may be NULL (zero).  The spectrum must be
+ * simple and, for m > n, nonzero; otherwise the result holds infinities.
+ * dG (ldd >= m) must not overlap the inputs.  Work arrays (3 n^2 + m n
+ * doubles per instance) are kept by the handle; the first call at a larger
+ * size allocates them (so it cannot be captured in a graph).
+ */
+int jevd_canonicalize(jevd_handle_t h, int batch, int m, int n, const double *lam, long long slam,
+                      const double *U, int ldu, long long su, const double *V, int ldv,
+                      long long sv, double *lam_out, double *U_out, double *V_out);
+int jevd_adjoint(jevd_handle_t h, int batch, int m, int n, const double *G, int ldg, long long sg,
+                 const signed char *J, long long sj, const double *lam, long long slam,
+                 const double *U, int ldu, long long su, const double *w, long long sw,
+                 const double *C, int ldc, long long sc, double *dG, int ldd, long long sd);
+
 /* Host-only argument check that jacobi_evd runs before any device work
  * (same rules; G, lambda and the handle are not examined).  Returns JEVD_OK
  * or JEVD_EINVAL.  No device work. */

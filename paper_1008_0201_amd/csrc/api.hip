@@ -71,6 +71,10 @@ struct jevd_handle_s {
     BlockWorkspace blk;
     KernelTimer timer;
     jevd_info info;
+
+    // adjoint work arrays: K, W, M' (n x n) and T (m x n) per instance
+    double *adjK = nullptr, *adjW = nullptr, *adjM = nullptr, *adjT = nullptr;
+    size_t capAdjK = 0, capAdjW = 0, capAdjM = 0, capAdjT = 0;
 };
 
 namespace {
@@ -244,6 +248,10 @@ int jevd_destroy(jevd_handle_t h)
     if (h->dpairs) (void)hipFree(h->dpairs);
     if (h->dstep) (void)hipFree(h->dstep);
     if (h->dslots) (void)hipFree(h->dslots);
+    if (h->adjK) (void)hipFree(h->adjK);
+    if (h->adjW) (void)hipFree(h->adjW);
+    if (h->adjM) (void)hipFree(h->adjM);
+    if (h->adjT) (void)hipFree(h->adjT);
     block_workspace_free(&h->blk);
     h->timer.release();
     delete h;
@@ -388,6 +396,43 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
     }
     if (sweeps) *sweeps = sweeps_done;
     return status;
+}
+
+int jevd_canonicalize(jevd_handle_t h, int batch, int m, int n, const double *lam, long long slam,
+                      const double *U, int ldu, long long su, const double *V, int ldv,
+                      long long sv, double *lam_out, double *U_out, double *V_out)
+{
+    if (!h || batch < 1 || n < 1 || m < n || !lam || !U || !lam_out || !U_out) return JEVD_EINVAL;
+    if (ldu < m || slam < n || su < (long long)ldu * n) return JEVD_EINVAL;
+    if ((V == nullptr) != (V_out == nullptr)) return JEVD_EINVAL;
+    if (V && (ldv < n || sv < (long long)ldv * n)) return JEVD_EINVAL;
+    if (batch > 65535) return JEVD_EINVAL;   // grid y limit of the launch
+    HIP_TRY(launch_canonical(batch, m, n, lam, slam, U, ldu, su, V, ldv, sv, lam_out, U_out, V_out,
+                             h->stream));
+    return JEVD_OK;
+}
+
+int jevd_adjoint(jevd_handle_t h, int batch, int m, int n, const double *G, int ldg, long long sg,
+                 const signed char *J, long long sj, const double *lam, long long slam,
+                 const double *U, int ldu, long long su, const double *w, long long sw,
+                 const double *C, int ldc, long long sc, double *dG, int ldd, long long sd)
+{
+    if (!h || batch < 1 || n < 1 || m < n || !G || !lam || !U || !dG) return JEVD_EINVAL;
+    if (ldg < m || ldu < m || ldd < m || slam < n) return JEVD_EINVAL;
+    if (sg < (long long)ldg * n || su < (long long)ldu * n || sd < (long long)ldd * n) return JEVD_EINVAL;
+    if (J && sj < n) return JEVD_EINVAL;
+    if (w && sw < n) return JEVD_EINVAL;
+    if (C && (ldc < m || sc < (long long)ldc * n)) return JEVD_EINVAL;
+    if (batch > 65535) return JEVD_EINVAL;   // grid z / y limit of the launches
+    const size_t nn = (size_t)n * n * batch, mn = (size_t)m * n * batch;
+    int st;
+    if ((st = grow_device(&h->adjK, &h->capAdjK, nn))) return st;
+    if ((st = grow_device(&h->adjW, &h->capAdjW, nn))) return st;
+    if ((st = grow_device(&h->adjM, &h->capAdjM, nn))) return st;
+    if ((st = grow_device(&h->adjT, &h->capAdjT, mn))) return st;
+    HIP_TRY(launch_adjoint(batch, m, n, G, ldg, sg, J, sj, lam, slam, U, ldu, su, w, sw, C, ldc, sc,
+                           dG, ldd, sd, h->adjK, h->adjW, h->adjM, h->adjT, h->stream));
+    return JEVD_OK;
 }
 
 int jevd_batch_destroy(jevd_batch_t p)

@@ -134,6 +134,15 @@ struct KernelTimer {
 hipError_t launch_pair_step(const PairStepArgs &a, hipStream_t st);
 
 struct BatchInst;
+hipError_t launch_canonical(int batch, int m, int n, const double *lam, long long slam,
+                            const double *U, int ldu, long long su, const double *V, int ldv,
+                            long long sv, double *lam_o, double *U_o, double *V_o, hipStream_t st);
+hipError_t launch_adjoint(int batch, int m, int n, const double *G, int ldg, long long sg,
+                          const signed char *J, long long sj, const double *lam, long long slam,
+                          const double *U, int ldu, long long su, const double *w, long long sw,
+                          const double *C, int ldc, long long sc, double *dG, int ldd,
+                          long long sd, double *wsK, double *wsW, double *wsM, double *wsT,
+                          hipStream_t st);
 hipError_t prepare_batch_kernel();  // once before the first launch (sets the LDS limit)
 hipError_t launch_batch(const BatchInst *inst, const int *order, int batch, int *queue,
                         int ordering, int max_sweeps, int accumulate_v, int *sweeps, int *status,

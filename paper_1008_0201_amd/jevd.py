@@ -19,7 +19,7 @@ INFO_MAX_SWEEPS = 64
 EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "jevd_validate",
            "jevd_get_info", "jevd_set_timing", "jevd_strerror", "jevd_ordering",
            "jevd_batch_create", "jevd_batch_run", "jevd_batch_results", "jevd_batch_destroy",
-           "jacobi_evd_batched")
+           "jacobi_evd_batched", "jevd_canonicalize", "jevd_adjoint")
 K_PAIR_STEP, K_GRAM, K_PIVOT_SOLVE, K_UPDATE = 0, 1, 2, 3
 
 
@@ -75,6 +75,11 @@ def lib():
         L.jevd_batch_results.argtypes = [_vp, _ip, _ip]
         L.jevd_batch_destroy.argtypes = [_vp]
         L.jacobi_evd_batched.argtypes = batch_args + [_ip, _ip]
+        _i, _ll = ctypes.c_int, ctypes.c_longlong
+        L.jevd_canonicalize.argtypes = [_vp, _i, _i, _i, _vp, _ll, _vp, _i, _ll, _vp, _i, _ll,
+                                        _vp, _vp, _vp]
+        L.jevd_adjoint.argtypes = [_vp, _i, _i, _i, _vp, _i, _ll, _vp, _ll, _vp, _ll, _vp, _i, _ll,
+                                   _vp, _ll, _vp, _i, _ll, _vp, _i, _ll]
         for name in EXPORTS:
             if name != "jevd_strerror":
                 getattr(L, name).restype = ctypes.c_int
@@ -218,6 +223,24 @@ def jacobi_evd_batched(h, m, n, G_ptrs, ldg, J_list, tol, opts, lam_ptrs, U_ptrs
     sw, stv = (ctypes.c_int * a.batch)(), (ctypes.c_int * a.batch)()
     st = lib().jacobi_evd_batched(*a.call_args(h, opts), sw, stv)
     return st, list(sw), list(stv)
+
+
+def _p(x):
+    return _vp(int(x)) if x else None
+
+
+def jevd_canonicalize(h, batch, m, n, lam, slam, U, ldu, su, V, ldv, sv, lam_out, U_out, V_out):
+    """Raw call; pointers are device addresses as ints (0 = NULL)."""
+    return lib().jevd_canonicalize(h, batch, m, n, _p(lam), slam, _p(U), ldu, su, _p(V), ldv, sv,
+                                   _p(lam_out), _p(U_out), _p(V_out))
+
+
+def jevd_adjoint(h, batch, m, n, G, ldg, sg, J, sj, lam, slam, U, ldu, su, w, sw, C, ldc, sc, dG,
+                 ldd, sd):
+    """Raw call; pointers are device addresses as ints (0 = NULL); J is a
+    device int8 array."""
+    return lib().jevd_adjoint(h, batch, m, n, _p(G), ldg, sg, _p(J), sj, _p(lam), slam, _p(U), ldu,
+                              su, _p(w), sw, _p(C), ldc, sc, _p(dG), ldd, sd)
 
 
 # ----------------------------------------------------------- torch front end

@@ -153,3 +153,22 @@ def graded_cols(m, n, k, decades=8.0):
     g = rng(k)
     B = g.standard_normal((m, n))
     return np.asfortranarray(B * (10.0 ** g.uniform(-decades, decades, size=n))[None, :])
+
+
+def adjoint_batch(count=256, n=128, k=5, m=None):
+    """Batch for the differentiated solve: count indefinite instances of the
+    uneven-batch recipe's odd kind at one size (G = B diag(10^U(-2,2)),
+    B ~ N(0,1), random J with 30-70 % negative signs), with the loss weights
+    w ~ N(0,1)^n and C ~ N(0,1)^{m x n} of L = sum_i w_i lambda_i + <C, U>.
+    Returns (G (count, m, n), J (count, n) int8, w (count, n), C (count, m, n))."""
+    g = rng(k)
+    m = n if m is None else m
+    G = np.empty((count, m, n))
+    J = np.empty((count, n), dtype=np.int8)
+    for i in range(count):
+        B = g.standard_normal((m, n))
+        G[i] = B * (10.0 ** g.uniform(-2.0, 2.0, size=n))[None, :]
+        J[i] = random_signature(n, g)
+    w = g.standard_normal((count, n))
+    C = g.standard_normal((count, m, n))
+    return G, J, w, C

@@ -1,0 +1,222 @@
+"""GPU parity of jevd_canonicalize and jevd_adjoint (through the C ABI) and
+of the autograd front end, against the oracle (oracle/adjoint.py) on the
+same inputs:
+  * canonical form: bit-exact (a permutation and signs);
+  * adjoint kernel fed the same G, J, lam, U as the oracle's formula:
+    relative Frobenius error <= 1e-11 (both FP64; they differ only in the
+    association of the products, and M' has entries up to
+    max |C| / min |lambda_i - lambda_k|, see test_adjoint_matches_oracle);
+  * the whole differentiated solve against the oracle's own solve + adjoint
+    on well separated spectra, and against central finite differences of the
+    GPU forward.
+Needs an MI355X and the built libjevd.so."""
+import numpy as np
+import pytest
+
+from paper_1008_0201_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch
+
+
+def oracle_adjoint():
+    import importlib
+    return importlib.import_module("oracle.adjoint")
+
+
+def recipe(count, m, n, k):
+    G, J, w, C = W.adjoint_batch(count=count, n=n, k=k, m=m)
+    return G, J, w, C
+
+
+def gpu_forward(torch, G, J):
+    from paper_1008_0201_amd.autograd import eigh_jacobi
+    Gt = torch.from_numpy(G).cuda()
+    Jt = None if J is None else torch.from_numpy(J).cuda()
+    lam, U = eigh_jacobi(Gt, Jt)
+    return lam.cpu().numpy(), U.cpu().numpy()
+
+
+@pytest.mark.parametrize("count,m,n", [(3, 40, 40), (4, 100, 70), (2, 150, 128), (5, 5, 5)])
+def test_canonical_matches_oracle_bit_exact(torch_dev, count, m, n):
+    torch = torch_dev
+    from paper_1008_0201_amd import jevd as B
+    A = oracle_adjoint()
+    G, J, w, C = recipe(count, m, n, 31 + n)
+    s = B.Solver()
+    try:
+        lams, Us, Vs = [], [], []
+        for b in range(count):
+            Gd = torch.from_numpy(np.ascontiguousarray(G[b].T)).cuda().T
+            lam, U, V, sweeps, st = s.evd(Gd, J[b], ordering=B.ORD_MODMODULUS)
+            lams.append(lam)
+            Us.append(U.T.contiguous())
+            Vs.append(V.T.contiguous())
+        lam = torch.stack(lams)
+        U = torch.stack(Us)          # (count, n, m): column-major instances
+        V = torch.stack(Vs)
+        lo, Uo, Vo = torch.empty_like(lam), torch.empty_like(U), torch.empty_like(V)
+        st = B.jevd_canonicalize(s.h, count, m, n, lam.data_ptr(), n, U.data_ptr(), m, m * n,
+                                 V.data_ptr(), n, n * n, lo.data_ptr(), Uo.data_ptr(), Vo.data_ptr())
+        assert st == 0
+        torch.cuda.synchronize()
+        for b in range(count):
+            l_ref, U_ref, V_ref, j = A.canonical(lam[b].cpu().numpy(), U[b].cpu().numpy().T,
+                                                 V[b].cpu().numpy().T, J[b])
+            assert np.array_equal(lo[b].cpu().numpy(), l_ref)
+            assert np.array_equal(Uo[b].cpu().numpy().T, U_ref)
+            assert np.array_equal(Vo[b].cpu().numpy().T, V_ref)
+    finally:
+        s.close()
+
+
+def test_canonical_ties_and_nonfinite(torch_dev):
+    """Equal eigenvalues keep their order; NaN sorts last; the ranks stay a
+    permutation (each slot written once)."""
+    torch = torch_dev
+    from paper_1008_0201_amd import jevd as B
+    n, m = 6, 6
+    lam = torch.tensor([[1.0, float("nan"), 1.0, -2.0, 3.0, 1.0]], dtype=torch.float64).cuda()
+    U = torch.eye(m, dtype=torch.float64).cuda().reshape(1, n, m) * torch.tensor(
+        [1.0, -1.0, 1.0, -1.0, 1.0, -1.0], dtype=torch.float64).cuda()[None, :, None]
+    lo, Uo = torch.full_like(lam, 7.0), torch.full_like(U, 7.0)
+    s = B.Solver()
+    try:
+        st = B.jevd_canonicalize(s.h, 1, m, n, lam.data_ptr(), n, U.data_ptr(), m, m * n, 0, n,
+                                 n * n, lo.data_ptr(), Uo.data_ptr(), 0)
+        assert st == 0
+        torch.cuda.synchronize()
+        got = lo.cpu().numpy()[0]
+        assert list(got[:5]) == [3.0, 1.0, 1.0, 1.0, -2.0] and np.isnan(got[5])
+        Uh = Uo.cpu().numpy()[0]         # rows = output columns
+        order = [4, 0, 2, 5, 3, 1]
+        for slot, src in enumerate(order):
+            e = np.zeros(m)
+            e[src] = 1.0                 # signs fixed: largest entry positive
+            assert np.array_equal(Uh[slot], e), slot
+    finally:
+        s.close()
+
+
+@pytest.mark.parametrize("count,m,n", [(4, 128, 128), (3, 150, 128), (3, 100, 70), (2, 7, 5),
+                                       (2, 200, 200)])
+def test_adjoint_matches_oracle(torch_dev, count, m, n):
+    """The adjoint kernel and the oracle's formula on the same (G, J, lam, U)."""
+    torch = torch_dev
+    from paper_1008_0201_amd import jevd as B
+    from paper_1008_0201_amd.autograd import eigh_jacobi
+    A = oracle_adjoint()
+    G, J, w, C = recipe(count, m, n, 57 + m + n)
+    Gt = torch.from_numpy(G).cuda()
+    lam, U = eigh_jacobi(Gt, torch.from_numpy(J).cuda())
+    Gc = Gt.transpose(1, 2).contiguous()
+    Uc = U.transpose(1, 2).contiguous()
+    wt = torch.from_numpy(w).cuda()
+    Ct = torch.from_numpy(np.ascontiguousarray(C.transpose(0, 2, 1))).cuda()
+    Jd = torch.from_numpy(J).cuda()
+    dG = torch.empty_like(Gc)
+    s = B.Solver()
+    try:
+        st = B.jevd_adjoint(s.h, count, m, n, Gc.data_ptr(), m, m * n, Jd.data_ptr(), n,
+                            lam.data_ptr(), n, Uc.data_ptr(), m, m * n, wt.data_ptr(), n,
+                            Ct.data_ptr(), m, m * n, dG.data_ptr(), m, m * n)
+        assert st == 0
+        torch.cuda.synchronize()
+    finally:
+        s.close()
+    lam_h, U_h, dG_h = lam.cpu().numpy(), U.cpu().numpy(), dG.cpu().numpy()
+    for b in range(count):
+        ref = A.adjoint(G[b], J[b], lam_h[b], U_h[b], w[b], C[b])
+        got = dG_h[b].T
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err <= 1e-11, (b, err)
+
+
+def test_adjoint_null_terms(torch_dev):
+    """w = 0 and C = 0 given as NULL: each part alone, and their sum."""
+    torch = torch_dev
+    from paper_1008_0201_amd.autograd import eigh_jacobi
+    A = oracle_adjoint()
+    G, J, w, C = recipe(2, 60, 48, 77)
+    Gt = torch.from_numpy(G).cuda().requires_grad_(True)
+    lam, U = eigh_jacobi(Gt, torch.from_numpy(J).cuda())
+    (gw,) = torch.autograd.grad((lam * torch.from_numpy(w).cuda()).sum(), Gt, retain_graph=True)
+    (gc,) = torch.autograd.grad((U * torch.from_numpy(C).cuda()).sum(), Gt)
+    lam_h, U_h = lam.detach().cpu().numpy(), U.detach().cpu().numpy()
+    for b in range(2):
+        rw = A.adjoint(G[b], J[b], lam_h[b], U_h[b], w[b], None)
+        rc = A.adjoint(G[b], J[b], lam_h[b], U_h[b], None, C[b])
+        assert np.linalg.norm(gw[b].cpu().numpy() - rw) <= 1e-11 * np.linalg.norm(rw)
+        assert np.linalg.norm(gc[b].cpu().numpy() - rc) <= 1e-11 * np.linalg.norm(rc)
+
+
+def separated(count, m, n, seed):
+    """Hyperbolic instances with min |lambda_i - lambda_k| >= 0.02 max |lambda|."""
+    g = np.random.default_rng(seed)
+    Gs, Js = [], []
+    while len(Gs) < count:
+        G = g.standard_normal((m, n)) * (10.0 ** g.uniform(-0.4, 0.4, size=n))[None, :]
+        J = np.ones(n, dtype=np.int8)
+        J[g.permutation(n)[: n // 2]] = -1
+        lam = np.linalg.eigvalsh(G @ np.diag(J.astype(float)) @ G.T)
+        lam = lam[np.argsort(-np.abs(lam))][:n]
+        gaps = np.abs(lam[:, None] - lam[None, :]) + np.eye(n) * 1e300
+        if gaps.min() >= 0.02 * np.abs(lam).max():
+            Gs.append(G)
+            Js.append(J)
+    return np.stack(Gs), np.stack(Js), g
+
+
+@pytest.mark.parametrize("m,n", [(8, 8), (12, 9)])
+def test_autograd_matches_oracle_solve_and_finite_differences(torch_dev, orc, m, n):
+    torch = torch_dev
+    from paper_1008_0201_amd.autograd import eigh_jacobi
+    A = oracle_adjoint()
+    G, J, g = separated(3, m, n, 100 + m)
+    w = g.standard_normal((3, n))
+    C = g.standard_normal((3, m, n))
+    Gt = torch.from_numpy(G).cuda().requires_grad_(True)
+    Jt = torch.from_numpy(J).cuda()
+    wt, Ct = torch.from_numpy(w).cuda(), torch.from_numpy(C).cuda()
+
+    def loss_gpu(Gx):
+        lam, U = eigh_jacobi(Gx, Jt)
+        return (lam * wt).sum(dim=1) + (U * Ct).sum(dim=(1, 2))
+
+    L = loss_gpu(Gt)
+    (grad,) = torch.autograd.grad(L.sum(), Gt)
+    grad = grad.cpu().numpy()
+    for b in range(3):
+        r = orc.jevd(G[b], J[b], None, orc.MODMODULUS, want_v=True)
+        lam_o, U_o, V_o, j = A.canonical(r.lam, r.U, r.V, J[b])
+        ref = A.adjoint(G[b], J[b], lam_o, U_o, w[b], C[b])
+        assert np.linalg.norm(grad[b] - ref) <= 1e-9 * np.linalg.norm(ref), b
+    h = 1e-6
+    for _ in range(3):
+        E = torch.from_numpy(g.standard_normal(G.shape)).cuda()
+        with torch.no_grad():
+            fd = ((loss_gpu(Gt + h * E) - loss_gpu(Gt - h * E)) / (2 * h)).cpu().numpy()
+        an = (torch.from_numpy(grad).cuda() * E).sum(dim=(1, 2)).cpu().numpy()
+        scale = np.linalg.norm(grad.reshape(3, -1), axis=1) * np.linalg.norm(
+            E.cpu().numpy().reshape(3, -1), axis=1)
+        assert np.all(np.abs(fd - an) <= 1e-7 * scale), (fd, an)
+
+
+def test_adjoint_invalid_arguments(torch_dev):
+    from paper_1008_0201_amd import jevd as B
+    s = B.Solver()
+    try:
+        assert B.jevd_adjoint(s.h, 1, 4, 5, 8, 4, 20, 0, 5, 8, 5, 8, 4, 20, 0, 5, 0, 4, 20, 8, 4,
+                              20) == B.JEVD_EINVAL          # m < n
+        assert B.jevd_adjoint(s.h, 1, 6, 5, 8, 5, 30, 0, 5, 8, 5, 8, 6, 30, 0, 5, 0, 6, 30, 8, 6,
+                              30) == B.JEVD_EINVAL          # ldg < m
+        assert B.jevd_canonicalize(s.h, 1, 6, 5, 8, 5, 8, 6, 30, 8, 5, 25, 8, 8,
+                                   0) == B.JEVD_EINVAL      # V without V_out
+    finally:
+        s.close()
