@@ -142,7 +142,7 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
  * treated exactly as jacobi_evd treats one (pointwise sweeps, the ordering,
  * tolerance and sweep limit of opts), in one persistent launch (Sec. 2.4:
  * instances, like disjoint pivots, are independent).  Meant for many small
- * and medium problems (n up to a few hundred).
+ * and medium problems (n up to a few hundred; n_i <= 4096).
  *
  * jevd_batch_create validates every instance (the rules of jacobi_evd;
  * JEVD_EINVAL before any device work), copies the J_i to the device and

@@ -470,7 +470,7 @@ int jevd_batch_create(jevd_handle_t h, int batch, const int *m, const int *n, do
         const int st = jevd_validate(m[i], n[i], ldg[i], J ? J[i] : nullptr, ti, &o, Ui,
                                      Ui ? ldu[i] : m[i], Vi, Vi ? ldv[i] : n[i]);
         if (st) return st;
-        if (!G[i]) return JEVD_EINVAL;
+        if (!G[i] || n[i] > kBatchMaxN) return JEVD_EINVAL;
         if (J && J[i]) jtotal += (size_t)n[i];
     }
     int dev = 0;

@@ -3,14 +3,17 @@
 //
 // Each workgroup takes instances from an atomic work queue, largest first
 // (the host sorts the queue by n_i^2 m_i, a longest-processing-time order),
-// and runs every sweep of an instance in-kernel, as k_small_solve does for a
-// single problem: the pairs of each parallel step of the ordering (closed
-// form, no tables) are dealt to the wavefronts, lanes run over rows, a
-// barrier separates steps, the sweep's rotation count decides convergence.
-// G_i and V_i live in LDS when they fit, otherwise they are transformed in
-// place in global memory (an instance of n = 256 holds 1 MiB, which the
-// 256 MiB Infinity Cache keeps on chip).  The eigenvalues lambda_i and the
-// normalised columns U_i are formed at the end of the instance.
+// and runs every sweep of an instance in-kernel.  A parallel step of the
+// ordering (closed form, no tables) runs in three barrier-separated phases:
+// Gram sums of all the step's pairs by lane groups, the transforms with one
+// lane per pair, then the rotations by the lane groups.  Handing a pair a
+// whole wavefront for its scalar part would repeat that arithmetic on 64
+// lanes, which made the step VALU-bound.  The sweep's rotation count decides
+// convergence.  G_i and V_i live in LDS when they fit, otherwise they are
+// transformed in place in global memory (an instance of n = 256 holds 1 MiB,
+// which the 256 MiB Infinity Cache keeps on chip).  The eigenvalues
+// lambda_i and the normalised columns U_i are formed at the end of the
+// instance.
 #include "../../include/jevd.h"
 #include "device_math.h"
 #include "jevd_internal.h"
@@ -29,7 +32,7 @@ struct BatchInst {
 };
 
 constexpr int kBatchWaves = 16;
-constexpr size_t kBatchLdsBytes = 160 * 1024 - 2048;
+constexpr size_t kBatchLdsBytes = 160 * 1024 - 256;   // the rest: static arrays
 
 // pairs of step st of the ordering over n columns (row-cyclic: one pair;
 // modulus family: closed form)
@@ -39,16 +42,358 @@ __device__ __forceinline__ int batch_step_pairs(int ordering, int n, int st)
     return modulus_step_pairs(n, st + 1, ordering == kOrdModModulus);
 }
 
+// Per-instance context of one workgroup.
+struct InstCtx {
+    int m, n;
+    double tol;
+    const signed char *J;  // n signs in LDS
+    double *sums;          // LDS: 3 per pair of a step (app, aqq, apq)
+    double *rotcs;         // LDS: 2 per pair (c, s)
+    int *flag;             // LDS: per pair: 0 none, 1 trigonometric, 2 hyperbolic
+};
+
+// LDS bytes kept beside G and V: the signs and the per-pair step arrays.
+// Rounded to 16 bytes so that the arrays at the top of LDS stay aligned.
+__host__ __device__ constexpr size_t batch_aux_bytes(int n)
+{
+    const size_t pairs = (size_t)n / 2 + 1;
+    return (pairs * 5 * sizeof(double) + pairs * sizeof(int) + (size_t)n + 15) & ~(size_t)15;
+}
+static_assert(kBatchLdsBytes % 16 == 0, "LDS top must stay 16-byte aligned");
+static_assert(batch_aux_bytes(kBatchMaxN) <= kBatchLdsBytes, "step arrays must fit in LDS");
+
+// Sum over groups of C consecutive lanes (C a power of two, <= 64); lane
+// c = 0 of each group ends with the group's total.
+__device__ __forceinline__ double group_sum(double x, int C)
+{
+    if (C >= 2) x += dpp_move<0xB1>(x);    // lane ^ 1
+    if (C >= 4) x += dpp_move<0x4E>(x);    // lane ^ 2
+    if (C >= 8) x += dpp_move<0x141>(x);   // 7 - i within 8
+    if (C >= 16) x += dpp_move<0x140>(x);  // 15 - i within 16
+    if (C >= 32) x += __shfl_xor(x, 16);
+    if (C >= 64) x += __shfl_xor(x, 32);
+    return x;
+}
+
+// One parallel step of the modulus family, in three phases separated by
+// barriers:
+//   1. Gram sums: each pair gets C lanes (C = 64 / pairs per wavefront),
+//      lane c sums rows c, c + C, ...; the C partial sums are reduced within
+//      the lane group and stored in LDS;
+//   2. transforms: one lane per pair decides and computes (c, s), so the
+//      scalar arithmetic of a pair runs once, not once per lane of a
+//      wavefront;
+//   3. rotation of the G (and V) column pairs by the same lane groups.
+// g and v are LDS or global pointers of one kind each (see the callers).
+__device__ __forceinline__ void modulus_step(double *g, long ldg, double *v, long ldv,
+                                             const InstCtx &c, int k, bool modified,
+                                             unsigned &rot, int &bad)
+{
+    constexpr int NW = kBatchWaves, BS = NW * 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = c.n, m = c.m;
+    const int np = modulus_step_pairs(n, k, modified);
+    int ppw = 1;  // pairs per wavefront and pass
+    while (ppw < 64 && NW * ppw < np) ppw *= 2;
+    const int C = 64 / ppw, per_pass = NW * ppw;
+    const int sub = lane / C, cl = lane % C;
+
+    for (int base = 0; base < np; base += per_pass) {
+        const int e = base + wave * ppw + sub;
+        int p = 0, q = 0;
+        const bool ok = e < np;
+        if (ok) modulus_pair(n, k, e, &p, &q);
+        double app = 0.0, aqq = 0.0, apq = 0.0;
+        if (ok) {
+            const double *gp = g + (size_t)p * ldg, *gq = g + (size_t)q * ldg;
+            for (int r = cl; r < m; r += C) {
+                const double x = gp[r], y = gq[r];
+                app = fma(x, x, app);
+                aqq = fma(y, y, aqq);
+                apq = fma(x, y, apq);
+            }
+        }
+        app = group_sum(app, C);
+        aqq = group_sum(aqq, C);
+        apq = group_sum(apq, C);
+        if (ok && cl == 0) {
+            c.sums[3 * e] = app;
+            c.sums[3 * e + 1] = aqq;
+            c.sums[3 * e + 2] = apq;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < np; e += BS) {
+        const double app = c.sums[3 * e], aqq = c.sums[3 * e + 1], apq = c.sums[3 * e + 2];
+        int f = 0;
+        if (!finite3(app, aqq, apq)) {
+            bad = 1;
+        } else if (needs_rotation(app, aqq, apq, c.tol)) {
+            int p, q;
+            modulus_pair(n, k, e, &p, &q);
+            const bool same = c.J[p] == c.J[q];
+            double cs, sn;
+            transform_params(app, aqq, apq, same, cs, sn);
+            c.rotcs[2 * e] = cs;
+            c.rotcs[2 * e + 1] = sn;
+            f = same ? 1 : 2;
+            ++rot;
+        }
+        c.flag[e] = f;
+    }
+    __syncthreads();
+    for (int base = 0; base < np; base += per_pass) {
+        const int e = base + wave * ppw + sub;
+        if (e >= np) continue;
+        const int f = c.flag[e];
+        if (f == 0) continue;
+        int p, q;
+        modulus_pair(n, k, e, &p, &q);
+        const double cs = c.rotcs[2 * e], sn = c.rotcs[2 * e + 1];
+        const bool same = f == 1;
+        double *gp = g + (size_t)p * ldg, *gq = g + (size_t)q * ldg;
+        for (int r = cl; r < m; r += C) {
+            double x = gp[r], y = gq[r];
+            rotate_elems(x, y, cs, sn, same);
+            gp[r] = x;
+            gq[r] = y;
+        }
+        if (v) {
+            double *vp = v + (size_t)p * ldv, *vq = v + (size_t)q * ldv;
+            for (int r = cl; r < n; r += C) {
+                double x = vp[r], y = vq[r];
+                rotate_elems(x, y, cs, sn, same);
+                vp[r] = x;
+                vq[r] = y;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// The step path for G in global memory: a wavefront takes one or two
+// pairs (p0, q0), (p1, q1) at a time and keeps their rows in registers from
+// the Gram sums to the rotation, so each element is read once per step; the
+// V rows are loaded with the G rows, so their latencies overlap.  Lane l
+// owns rows l, l + 64, ..., l + 64 (R - 1) (m <= 64 R).  The transform is
+// computed on the whole wavefront (one useful value), which is affordable
+// here because the step is bound by the global traffic.
+template <int R>
+__device__ __forceinline__ void two_pairs(double *g, long ldg, double *v, long ldv,
+                                          const InstCtx &c, int p0, int q0, bool has1, int p1,
+                                          int q1, int lane, unsigned &rot, int &bad)
+{
+    const int pp[2] = {p0, p1}, qq[2] = {q0, q1};
+    double a[2][R], b[2][R], va[2][R], vb[2][R];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !has1) break;
+        const double *gp = g + (size_t)pp[k] * ldg, *gq = g + (size_t)qq[k] * ldg;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = lane + 64 * i;
+            a[k][i] = r < c.m ? gp[r] : 0.0;
+            b[k][i] = r < c.m ? gq[r] : 0.0;
+        }
+        if (v) {
+            const double *vp = v + (size_t)pp[k] * ldv, *vq = v + (size_t)qq[k] * ldv;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = lane + 64 * i;
+                va[k][i] = r < c.n ? vp[r] : 0.0;
+                vb[k][i] = r < c.n ? vq[r] : 0.0;
+            }
+        }
+    }
+    double app[2] = {0.0, 0.0}, aqq[2] = {0.0, 0.0}, apq[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !has1) break;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            app[k] = fma(a[k][i], a[k][i], app[k]);
+            aqq[k] = fma(b[k][i], b[k][i], aqq[k]);
+            apq[k] = fma(a[k][i], b[k][i], apq[k]);
+        }
+        app[k] = wave_sum(app[k]);
+        aqq[k] = wave_sum(aqq[k]);
+        apq[k] = wave_sum(apq[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !has1) break;
+        if (!finite3(app[k], aqq[k], apq[k])) {
+            bad = 1;
+            continue;
+        }
+        if (!needs_rotation(app[k], aqq[k], apq[k], c.tol)) continue;
+        const bool same = c.J[pp[k]] == c.J[qq[k]];
+        double cs, sn;
+        transform_params(app[k], aqq[k], apq[k], same, cs, sn);
+        double *gp = g + (size_t)pp[k] * ldg, *gq = g + (size_t)qq[k] * ldg;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = lane + 64 * i;
+            rotate_elems(a[k][i], b[k][i], cs, sn, same);
+            if (r < c.m) {
+                gp[r] = a[k][i];
+                gq[r] = b[k][i];
+            }
+        }
+        if (v) {
+            double *vp = v + (size_t)pp[k] * ldv, *vq = v + (size_t)qq[k] * ldv;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = lane + 64 * i;
+                rotate_elems(va[k][i], vb[k][i], cs, sn, same);
+                if (r < c.n) {
+                    vp[r] = va[k][i];
+                    vq[r] = vb[k][i];
+                }
+            }
+        }
+        if (lane == 0) ++rot;
+    }
+}
+
+// One step over G in global memory by the register path (R > 0; two pairs
+// per wavefront for R <= 2, one for R = 4, registers permitting).
+template <int R>
+__device__ __forceinline__ void global_step(double *g, long ldg, double *v, long ldv,
+                                            const InstCtx &c, int k, bool modified, unsigned &rot,
+                                            int &bad)
+{
+    constexpr int NW = kBatchWaves;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int np = modulus_step_pairs(c.n, k, modified);
+    if constexpr (R <= 2) {
+        for (int e = wave; e < np; e += 2 * NW) {
+            int p0, q0, p1 = 0, q1 = 0;
+            modulus_pair(c.n, k, e, &p0, &q0);
+            const bool has1 = e + NW < np;
+            if (has1) modulus_pair(c.n, k, e + NW, &p1, &q1);
+            two_pairs<R>(g, ldg, v, ldv, c, p0, q0, has1, p1, q1, lane, rot, bad);
+        }
+    } else {
+        for (int e = wave; e < np; e += NW) {
+            int p, q;
+            modulus_pair(c.n, k, e, &p, &q);
+            two_pairs<R>(g, ldg, v, ldv, c, p, q, false, 0, 0, lane, rot, bad);
+        }
+    }
+    __syncthreads();
+}
+
+// One pair with rows looped over by one wavefront (the row-cyclic path).
+__device__ __forceinline__ void one_pair_loop(double *g, long ldg, double *v, long ldv,
+                                              const InstCtx &c, int p, int q, int lane,
+                                              unsigned &rot, int &bad)
+{
+    double *gp = g + (size_t)p * ldg, *gq = g + (size_t)q * ldg;
+    double app = 0.0, aqq = 0.0, apq = 0.0;
+    for (int r = lane; r < c.m; r += 64) {
+        const double x = gp[r], y = gq[r];
+        app = fma(x, x, app);
+        aqq = fma(y, y, aqq);
+        apq = fma(x, y, apq);
+    }
+    app = wave_sum(app);
+    aqq = wave_sum(aqq);
+    apq = wave_sum(apq);
+    if (!finite3(app, aqq, apq)) {
+        bad = 1;
+        return;
+    }
+    if (!needs_rotation(app, aqq, apq, c.tol)) return;
+    const bool same = c.J[p] == c.J[q];
+    double cs, sn;
+    transform_params(app, aqq, apq, same, cs, sn);
+    for (int r = lane; r < c.m; r += 64) {
+        double x = gp[r], y = gq[r];
+        rotate_elems(x, y, cs, sn, same);
+        gp[r] = x;
+        gq[r] = y;
+    }
+    if (v) {
+        double *vp = v + (size_t)p * ldv, *vq = v + (size_t)q * ldv;
+        for (int r = lane; r < c.n; r += 64) {
+            double x = vp[r], y = vq[r];
+            rotate_elems(x, y, cs, sn, same);
+            vp[r] = x;
+            vq[r] = y;
+        }
+    }
+    if (lane == 0) ++rot;
+}
+
+// All sweeps of one instance on (g, v); returns the status and sets sweeps.
+// R = 0: the phased step (G in LDS, or m > 256); R > 0: the register step.
+template <int R>
+__device__ __forceinline__ int sweep_instance(double *g, long ldg, double *v, long ldv,
+                                              const InstCtx &c, int ordering, int max_sweeps,
+                                              int &sweeps, unsigned *s_rot, int *s_bad)
+{
+    constexpr int NW = kBatchWaves;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = c.n;
+    int sweep = 0, status = JEVD_ENOCONV;
+    int bad = 0;
+    while (sweep < max_sweeps) {
+        unsigned rot = 0;
+        if (ordering == kOrdRowCyclic) {
+            // one pair at a time, in wavefront 0 (no barrier between steps)
+            if (wave == 0)
+                for (int p = 0; p < n - 1; ++p)
+                    for (int q = p + 1; q < n; ++q) one_pair_loop(g, ldg, v, ldv, c, p, q, lane, rot, bad);
+        } else {
+            for (int k = 1; k <= n; ++k) {
+                if constexpr (R > 0) global_step<R>(g, ldg, v, ldv, c, k, ordering == kOrdModModulus, rot, bad);
+                else modulus_step(g, ldg, v, ldv, c, k, ordering == kOrdModModulus, rot, bad);
+            }
+        }
+        // workgroup totals: rotations and the non-finite flag
+        unsigned r = rot;
+        int b = bad;
+        for (int off = 32; off > 0; off >>= 1) {
+            r += __shfl_xor(r, off);
+            b |= __shfl_xor(b, off);
+        }
+        if (lane == 0) {
+            s_rot[wave] = r;
+            s_bad[wave] = b;
+        }
+        __syncthreads();
+        unsigned tot = 0;
+        int nf = 0;
+        for (int w = 0; w < NW; ++w) {
+            tot += s_rot[w];
+            nf |= s_bad[w];
+        }
+        ++sweep;
+        __syncthreads();
+        if (nf) {
+            status = JEVD_ENONFINITE;
+            break;
+        }
+        if (tot == 0) {
+            status = JEVD_OK;
+            break;
+        }
+    }
+    sweeps = sweep;
+    return status;
+}
+
 __global__ __launch_bounds__(kBatchWaves * 64) void k_batch_solve(
     const BatchInst *__restrict__ inst, const int *__restrict__ order, int batch,
     int *__restrict__ queue, int ordering, int max_sweeps, int accumulate_v,
     int *__restrict__ sweeps_out, int *__restrict__ status_out)
 {
-    constexpr int NW = kBatchWaves;
-    constexpr int BS = NW * 64;
+    constexpr int BS = kBatchWaves * 64;
     extern __shared__ double lds[];
-    __shared__ int s_idx, s_nonfinite;
-    __shared__ unsigned long long s_rot[NW];
+    __shared__ int s_idx;
+    __shared__ unsigned s_rot[kBatchWaves];
+    __shared__ int s_bad[kBatchWaves];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     for (;;) {
@@ -60,129 +405,73 @@ __global__ __launch_bounds__(kBatchWaves * 64) void k_batch_solve(
         const int which = order[idx];
         const BatchInst d = inst[which];
         const int m = d.m, n = d.n;
-        // where the instance lives while it is transformed
+        // where the instance lives while it is transformed: G (and V) in LDS
+        // when they fit beside the signs and step arrays at the top of LDS,
+        // else in place in global memory
+        const size_t aux = batch_aux_bytes(n);
         const size_t gbytes = (size_t)m * n * sizeof(double);
         const size_t vbytes = d.V ? (size_t)n * n * sizeof(double) : 0;
-        const bool lg = gbytes <= kBatchLdsBytes;
-        const bool lv = d.V && gbytes + vbytes <= kBatchLdsBytes;
-        double *g = d.G;
-        long ldg = d.ldg;
-        double *v = d.V;
-        long ldv = d.ldv;
-        if (lg) {
-            g = lds;
-            ldg = m;
-            for (int e = tid; e < m * n; e += BS) g[e] = d.G[(size_t)(e / m) * d.ldg + (e % m)];
-        }
+        const bool lg = gbytes + aux <= kBatchLdsBytes;
+        const bool lv = d.V && gbytes + vbytes + aux <= kBatchLdsBytes;
+        const size_t pairs = (size_t)n / 2 + 1;
+        char *top = (char *)lds + (kBatchLdsBytes - aux);
+        InstCtx c;
+        c.m = m;
+        c.n = n;
+        c.tol = d.tol;
+        c.sums = (double *)top;
+        c.rotcs = c.sums + 3 * pairs;
+        c.flag = (int *)(c.rotcs + 2 * pairs);
+        signed char *sJ = (signed char *)(c.flag + pairs);
+        c.J = sJ;
+        for (int e = tid; e < n; e += BS) sJ[e] = (d.J && d.J[e] < 0) ? -1 : 1;
+        if (lg)
+            for (int e = tid; e < m * n; e += BS) lds[e] = d.G[(size_t)(e / m) * d.ldg + (e % m)];
         if (d.V) {
-            if (lv) {
-                v = lds + (size_t)m * n;
-                ldv = n;
-            }
+            double *v = lv ? lds + (size_t)m * n : d.V;
+            const long ldv = lv ? n : d.ldv;
             for (int e = tid; e < n * n; e += BS) {
-                const int r = e % n, c = e / n;
-                const double x = accumulate_v ? d.V[(size_t)c * d.ldv + r] : (r == c ? 1.0 : 0.0);
-                v[(size_t)c * ldv + r] = x;
+                const int r = e % n, cc = e / n;
+                const double x = accumulate_v ? d.V[(size_t)cc * d.ldv + r] : (r == cc ? 1.0 : 0.0);
+                v[(size_t)cc * ldv + r] = x;
             }
         }
-        if (tid == 0) s_nonfinite = 0;
         __syncthreads();
-
-        const int nsteps = ordering == kOrdRowCyclic ? n * (n - 1) / 2 : n;
-        int sweep = 0, status = JEVD_ENOCONV;
-        while (sweep < max_sweeps) {
-            unsigned long long rot = 0;
-            int rp = 0, rq = 1;  // row-cyclic state: the pair of the current step
-            for (int st = 0; st < nsteps; ++st) {
-                const int np = batch_step_pairs(ordering, n, st);
-                for (int e = wave; e < np; e += NW) {
-                    int p, q;
-                    if (ordering == kOrdRowCyclic) {
-                        p = rp;
-                        q = rq;
-                    } else {
-                        modulus_pair(n, st + 1, e, &p, &q);
-                    }
-                    double *gp = g + (size_t)p * ldg, *gq = g + (size_t)q * ldg;
-                    double app = 0.0, aqq = 0.0, apq = 0.0;
-                    for (int r = lane; r < m; r += 64) {
-                        const double a = gp[r], b = gq[r];
-                        app = fma(a, a, app);
-                        aqq = fma(b, b, aqq);
-                        apq = fma(a, b, apq);
-                    }
-                    app = wave_sum(app);
-                    aqq = wave_sum(aqq);
-                    apq = wave_sum(apq);
-                    if (!finite3(app, aqq, apq)) {
-                        s_nonfinite = 1;
-                        continue;
-                    }
-                    if (!needs_rotation(app, aqq, apq, d.tol)) continue;
-                    const bool same = (d.J == nullptr) || (d.J[p] == d.J[q]);
-                    double c, s;
-                    transform_params(app, aqq, apq, same, c, s);
-                    for (int r = lane; r < m; r += 64) {
-                        double a = gp[r], b = gq[r];
-                        rotate_elems(a, b, c, s, same);
-                        gp[r] = a;
-                        gq[r] = b;
-                    }
-                    if (v) {
-                        double *vp = v + (size_t)p * ldv, *vq = v + (size_t)q * ldv;
-                        for (int r = lane; r < n; r += 64) {
-                            double a = vp[r], b = vq[r];
-                            rotate_elems(a, b, c, s, same);
-                            vp[r] = a;
-                            vq[r] = b;
-                        }
-                    }
-                    ++rot;
-                }
-                if (ordering == kOrdRowCyclic) {
-                    if (++rq == n) {
-                        ++rp;
-                        rq = rp + 1;
-                    }
-                } else {
-                    __syncthreads();
-                }
-            }
-            if (lane == 0) s_rot[wave] = rot;
-            __syncthreads();
-            unsigned long long tot = 0;
-            for (int w = 0; w < NW; ++w) tot += s_rot[w];
-            const int nf = s_nonfinite;
-            ++sweep;
-            __syncthreads();
-            if (nf) {
-                status = JEVD_ENONFINITE;
-                break;
-            }
-            if (tot == 0) {
-                status = JEVD_OK;
-                break;
-            }
-        }
+        int sweep = 0, status;
+        if (lg && lv)
+            status = sweep_instance<0>(lds, m, lds + (size_t)m * n, n, c, ordering, max_sweeps, sweep,
+                                       s_rot, s_bad);
+        else if (lg)
+            status = sweep_instance<0>(lds, m, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
+                                       s_bad);
+        else if (m <= 128)
+            status = sweep_instance<2>(d.G, d.ldg, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
+                                       s_bad);
+        else if (m <= 256)
+            status = sweep_instance<4>(d.G, d.ldg, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
+                                       s_bad);
+        else
+            status = sweep_instance<0>(d.G, d.ldg, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
+                                       s_bad);
         // the final iterate back to G (and V), then lambda_i = j_i ||g_i||^2 and
         // u_i = g_i / ||g_i|| (U may be G itself)
         if (lg)
-            for (int e = tid; e < m * n; e += BS) d.G[(size_t)(e / m) * d.ldg + (e % m)] = g[e];
+            for (int e = tid; e < m * n; e += BS) d.G[(size_t)(e / m) * d.ldg + (e % m)] = lds[e];
         if (lv)
             for (int e = tid; e < n * n; e += BS) {
-                const int r = e % n, c = e / n;
-                d.V[(size_t)c * d.ldv + r] = v[(size_t)c * ldv + r];
+                const int r = e % n, cc = e / n;
+                d.V[(size_t)cc * d.ldv + r] = lds[(size_t)m * n + (size_t)cc * n + r];
             }
         __syncthreads();
-        for (int c = wave; c < n; c += NW) {
-            const double *gc = g + (size_t)c * ldg;
+        for (int cc = wave; cc < n; cc += kBatchWaves) {
+            const double *gc = lg ? lds + (size_t)cc * m : d.G + (size_t)cc * d.ldg;
             double s2 = 0.0;
             for (int r = lane; r < m; r += 64) s2 = fma(gc[r], gc[r], s2);
             s2 = wave_sum(s2);
-            if (d.lambda && lane == 0) d.lambda[c] = (d.J && d.J[c] < 0) ? -s2 : s2;
+            if (d.lambda && lane == 0) d.lambda[cc] = sJ[cc] < 0 ? -s2 : s2;
             if (d.U) {
                 const double nrm = sqrt(s2);
-                double *uc = d.U + (size_t)c * d.ldu;
+                double *uc = d.U + (size_t)cc * d.ldu;
                 for (int r = lane; r < m; r += 64) uc[r] = (s2 > 0.0) ? gc[r] / nrm : 0.0;
             }
         }

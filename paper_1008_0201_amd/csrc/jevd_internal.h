@@ -143,6 +143,7 @@ hipError_t launch_adjoint(int batch, int m, int n, const double *G, int ldg, lon
                           const double *C, int ldc, long long sc, double *dG, int ldd,
                           long long sd, double *wsK, double *wsW, double *wsM, double *wsT,
                           hipStream_t st);
+constexpr int kBatchMaxN = 4096;   // largest n_i of a batched solve
 hipError_t prepare_batch_kernel();  // once before the first launch (sets the LDS limit)
 hipError_t launch_batch(const BatchInst *inst, const int *order, int batch, int *queue,
                         int ordering, int max_sweeps, int accumulate_v, int *sweeps, int *status,
