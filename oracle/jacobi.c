@@ -266,7 +266,8 @@ int SFX(orc_jevd)(int m, int n, double *G, int ldg, const signed char *J, double
 }
 
 /* ------------------------------------------------------------------------
- * Block one-sided Jacobi (Sec. 2.2-2.3, Alg. 3.4 with unpivoted Cholesky).
+ * Block one-sided Jacobi (Sec. 2.2-2.3, Alg. 3.4 with the unpivoted Cholesky,
+ * or with the sign-pivoted Cholesky of Alg. 3.3: HBSC / HFSC).
  *
  * Columns are split into N = 2 ceil(n / (2b)) block columns whose widths
  * differ by at most one (Sec. 3: uniform partition).  Block pairs (I, J)
@@ -288,6 +289,12 @@ int SFX(orc_jevd)(int m, int n, double *G, int ldg, const signed char *J, double
  *      Sec. 2.3).
  * If the Cholesky factorisation breaks down (a non-positive pivot), step 4
  * runs on the columns of G_P itself instead of R.
+ * With sign pivoting, step 3 is P^T A_P P = R_S^T R_S (Alg. 3.3), step 4
+ * runs on R_S with the signs of the permuted positions (positive first),
+ * V_P = P V' (the permutation applied to the rows of the accumulated V'),
+ * and after the update column c of the block carries the sign of position
+ * c.  Block-oriented steps other than the first of a sweep pair the first
+ * w_I positions of R_S with the others.
  * Inner orderings: over all w columns the modified modulus ordering (odd
  * modulus for odd w); over the I x J pairs the bipartite shift: step
  * s = 0..L-1 (L = max(w_I, w_J)) holds the pairs (k, w_I + (k+s) mod L)
@@ -328,11 +335,153 @@ static int cross_ordering(int wi, int wj, int *step_start, int *pairs)
     return L;
 }
 
+/* ------------------------------------------------------------------------
+ * Sign-pivoted Cholesky factorisation of a pivot Gram (Sec. 3.2, (3.5)-(3.7),
+ * Alg. 3.3), used by the HBSC / HFSC variants.
+ *
+ * Cholesky with diagonal pivoting of a k x k symmetric matrix S (column-major,
+ * ld lds, read only): P^T S P = R^T R with R upper triangular; at step j the
+ * pivot is the largest remaining diagonal entry of the updated matrix (the
+ * first one on ties).  perm[c] is the row/column of S moved to position c.
+ * Returns 1 on a non-positive pivot (no factor), else 0.
+ */
+static int pivoted_cholesky(int k, const real *S, int lds, real *R, int ldr, int *perm, real *W)
+{
+    for (int c = 0; c < k; ++c) {
+        perm[c] = c;
+        for (int r = 0; r < k; ++r) W[(size_t)c * k + r] = S[(size_t)c * lds + r];
+    }
+    for (int c = 0; c < k; ++c)
+        for (int r = 0; r < k; ++r) R[(size_t)c * ldr + r] = 0;
+    for (int j = 0; j < k; ++j) {
+        int t = j;
+        for (int i = j + 1; i < k; ++i)
+            if (W[(size_t)i * k + i] > W[(size_t)t * k + t]) t = i;
+        if (t != j) {   /* symmetric swap of rows and columns j, t of W */
+            for (int r = 0; r < k; ++r) {
+                real x = W[(size_t)j * k + r];
+                W[(size_t)j * k + r] = W[(size_t)t * k + r];
+                W[(size_t)t * k + r] = x;
+            }
+            for (int c = 0; c < k; ++c) {
+                real x = W[(size_t)c * k + j];
+                W[(size_t)c * k + j] = W[(size_t)c * k + t];
+                W[(size_t)c * k + t] = x;
+            }
+            for (int r = 0; r < j; ++r) {   /* rows of R already formed */
+                real x = R[(size_t)j * ldr + r];
+                R[(size_t)j * ldr + r] = R[(size_t)t * ldr + r];
+                R[(size_t)t * ldr + r] = x;
+            }
+            int x = perm[j];
+            perm[j] = perm[t];
+            perm[t] = x;
+        }
+        real d = W[(size_t)j * k + j];
+        if (!(d > 0)) return 1;
+        real rjj = R_SQRT(d);
+        R[(size_t)j * ldr + j] = rjj;
+        for (int l = j + 1; l < k; ++l) R[(size_t)l * ldr + j] = W[(size_t)l * k + j] / rjj;
+        for (int l = j + 1; l < k; ++l)
+            for (int i = j + 1; i < k; ++i)
+                W[(size_t)l * k + i] = W[(size_t)l * k + i] - R[(size_t)i * ldr + j] * R[(size_t)l * ldr + j];
+    }
+    return 0;
+}
+
+/*
+ * Alg. 3.3 on the w x w pivot Gram A (column-major, ld w) with signs JP.
+ * The columns with j = +1 (in their order) form block 1, those with j = -1
+ * block 2 ((3.5)):
+ *   P1^T A11 P1 = R11^T R11           (diagonal pivoting)
+ *   R11^T R12 = P1^T A12              (forward substitution)
+ *   S = A22 - R12^T R12,  P2^T S P2 = R22^T R22   ((3.7))
+ *   R_S = [R11, R12 P2; 0, R22], then the columns of its second block
+ *   column (and P2) are reversed.
+ * Outputs RS (w x w, ld w), perm (position c of R_S holds pivot column
+ * perm[c]) and npos; the sign of position c is +1 for c < npos, else -1.
+ * Returns 1 if a factorisation broke down, else 0.  W needs 3 w^2 reals,
+ * iw 3 w ints.
+ */
+static int sign_pivoted_cholesky(int w, const real *A, const signed char *JP, real *RS, int *perm,
+                                 int *npos_out, real *W, int *iw)
+{
+    int *pos = iw, *neg = iw + w, *pp = iw + 2 * w;
+    int np = 0, nn = 0;
+    for (int k = 0; k < w; ++k) {
+        if (JP[k] > 0) pos[np++] = k;
+        else neg[nn++] = k;
+    }
+    *npos_out = np;
+    real *S = W, *R = W + (size_t)w * w, *work = W + 2 * (size_t)w * w;
+    for (int c = 0; c < w; ++c)
+        for (int r = 0; r < w; ++r) RS[(size_t)c * w + r] = 0;
+    /* R11 */
+    for (int c = 0; c < np; ++c)
+        for (int r = 0; r < np; ++r) S[(size_t)c * np + r] = A[(size_t)pos[c] * w + pos[r]];
+    if (np > 0) {
+        if (pivoted_cholesky(np, S, np, R, np, pp, work)) return 1;
+        for (int c = 0; c < np; ++c) {
+            perm[c] = pos[pp[c]];
+            for (int r = 0; r <= c; ++r) RS[(size_t)c * w + r] = R[(size_t)c * np + r];
+        }
+    }
+    /* R12: R11^T X = P1^T A12 (X is np x nn), by forward substitution */
+    for (int c = 0; c < nn; ++c)
+        for (int r = 0; r < np; ++r) {
+            real sum = A[(size_t)neg[c] * w + perm[r]];
+            for (int k = 0; k < r; ++k) sum = sum - RS[(size_t)r * w + k] * RS[(size_t)(np + c) * w + k];
+            RS[(size_t)(np + c) * w + r] = sum / RS[(size_t)r * w + r];
+        }
+    /* S = A22 - R12^T R12 */
+    for (int c = 0; c < nn; ++c)
+        for (int r = 0; r < nn; ++r) {
+            real sum = A[(size_t)neg[c] * w + neg[r]];
+            for (int k = 0; k < np; ++k)
+                sum = sum - RS[(size_t)(np + r) * w + k] * RS[(size_t)(np + c) * w + k];
+            S[(size_t)c * nn + r] = sum;
+        }
+    if (nn > 0) {
+        if (pivoted_cholesky(nn, S, nn, R, nn, pp, work)) return 1;
+        /* R_S,2 = [R12 P2; R22] with its columns (and P2) reversed */
+        real *X = work;   /* R12 before the permutation: np x nn */
+        for (int c = 0; c < nn; ++c)
+            for (int r = 0; r < np; ++r) X[(size_t)c * np + r] = RS[(size_t)(np + c) * w + r];
+        for (int c = 0; c < nn; ++c) {
+            const int src = pp[nn - 1 - c];         /* reversed P2 */
+            for (int r = 0; r < np; ++r) RS[(size_t)(np + c) * w + r] = X[(size_t)src * np + r];
+            for (int r = 0; r < nn; ++r)
+                RS[(size_t)(np + c) * w + np + r] = R[(size_t)(nn - 1 - c) * nn + r];
+            perm[np + c] = neg[src];
+        }
+    }
+    return 0;
+}
+
+/* Test hook: Alg. 3.3 on one w x w Gram. */
+int SFX(orc_sp_cholesky)(int w, const double *A, const signed char *JP, double *RS, int *perm,
+                         int *npos_out)
+{
+    if (w < 1 || !A || !JP || !RS || !perm || !npos_out) return ORC_EINVAL;
+    real *Ar = (real *)malloc(sizeof(real) * (size_t)w * w);
+    real *Rr = (real *)malloc(sizeof(real) * (size_t)w * w);
+    real *W = (real *)malloc(sizeof(real) * 3 * (size_t)w * w);
+    int *iw = (int *)malloc(sizeof(int) * 3 * (size_t)w);
+    int st = ORC_ENOMEM;
+    if (Ar && Rr && W && iw) {
+        for (size_t e = 0; e < (size_t)w * w; ++e) Ar[e] = (real)A[e];
+        st = sign_pivoted_cholesky(w, Ar, JP, Rr, perm, npos_out, W, iw) ? 1 : ORC_OK;
+        for (size_t e = 0; e < (size_t)w * w; ++e) RS[e] = (double)Rr[e];
+    }
+    free(Ar); free(Rr); free(W); free(iw);
+    return st;
+}
+
 static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *J, double tol,
-                           int b, int full_block, int max_sweeps, int max_inner,
+                           int b, int full_block, int sign_pivot, int max_sweeps, int max_inner,
                            int accumulate_v, double *lambda, double *V, int ldv,
                            int *sweeps_out, long long *rot_per_sweep,
-                           long long *nbreakdown_out, int max_steps);
+                           long long *nbreakdown_out, int max_steps, signed char *J_out);
 
 int SFX(orc_block_jevd)(int m, int n, double *G, int ldg, const signed char *J, double tol,
                         int b, int full_block, int max_sweeps, int max_inner,
@@ -340,9 +489,24 @@ int SFX(orc_block_jevd)(int m, int n, double *G, int ldg, const signed char *J, 
                         int *sweeps_out, long long *rot_per_sweep,
                         long long *nbreakdown_out)
 {
-    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, max_sweeps, max_inner,
+    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, 0, max_sweeps, max_inner,
                            accumulate_v, lambda, V, ldv, sweeps_out, rot_per_sweep,
-                           nbreakdown_out, -1);
+                           nbreakdown_out, -1, NULL);
+}
+
+/* The same with the sign-pivoted Cholesky of Alg. 3.3 (HBSC / HFSC; for
+ * J = I the diagonally pivoted Cholesky).  The pivoting permutes the
+ * columns of each transformed pivot block and their signs; J_out (n, may be
+ * NULL) receives the final signs, and lambda_i carries them. */
+int SFX(orc_block_jevd_sp)(int m, int n, double *G, int ldg, const signed char *J, double tol,
+                           int b, int full_block, int max_sweeps, int max_inner,
+                           int accumulate_v, double *lambda, double *V, int ldv,
+                           int *sweeps_out, long long *rot_per_sweep,
+                           long long *nbreakdown_out, signed char *J_out)
+{
+    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, 1, max_sweeps, max_inner,
+                           accumulate_v, lambda, V, ldv, sweeps_out, rot_per_sweep,
+                           nbreakdown_out, -1, J_out);
 }
 
 /* The first max_steps outer steps of the first sweep only: a bounded sample
@@ -352,15 +516,15 @@ int SFX(orc_block_steps)(int m, int n, double *G, int ldg, const signed char *J,
                          int b, int full_block, int max_inner, int max_steps)
 {
     int sweeps = 0;
-    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, 1, max_inner, 0, NULL, NULL,
-                           n, &sweeps, NULL, NULL, max_steps);
+    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, 0, 1, max_inner, 0, NULL, NULL,
+                           n, &sweeps, NULL, NULL, max_steps, NULL);
 }
 
 static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *J, double tol,
-                           int b, int full_block, int max_sweeps, int max_inner,
+                           int b, int full_block, int sign_pivot, int max_sweeps, int max_inner,
                            int accumulate_v, double *lambda, double *V, int ldv,
                            int *sweeps_out, long long *rot_per_sweep,
-                           long long *nbreakdown_out, int max_steps)
+                           long long *nbreakdown_out, int max_steps, signed char *J_out)
 {
     int st = check_args(m, n, ldg, J, ldv, V);
     if (st) return st;
@@ -384,13 +548,21 @@ static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *
     real *R = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
     real *VP = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
     signed char *JP = (signed char *)malloc((size_t)wmax);
+    signed char *JS = (signed char *)malloc((size_t)wmax);
+    signed char *Jc = (signed char *)malloc((size_t)n);
     int *colp = (int *)malloc(sizeof(int) * (size_t)wmax);
+    int *perm = (int *)malloc(sizeof(int) * (size_t)wmax);
+    int *iw = (int *)malloc(sizeof(int) * 3 * (size_t)wmax);
+    real *SW = (real *)malloc(sizeof(real) * 3 * (size_t)wmax * wmax);
+    real *VQ = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
     if (!bstart || !ostart || !opairs || !istart || !ipairs || !Gr || (V && !Vr) ||
-        !GP || !VB || !AP || !R || !VP || !JP || !colp) {
+        !GP || !VB || !AP || !R || !VP || !JP || !JS || !Jc || !colp || !perm || !iw || !SW ||
+        !VQ) {
         st = ORC_ENOMEM;
         goto out;
     }
     orc_ordering(N, 2, ostart, opairs, NULL);
+    for (int i = 0; i < n; ++i) Jc[i] = (J && J[i] < 0) ? -1 : 1;
     bstart[0] = 0;
     for (int k = 0; k < N; ++k) bstart[k + 1] = bstart[k] + n / N + (k < n % N ? 1 : 0);
     for (int i = 0; i < n; ++i)
@@ -415,7 +587,7 @@ static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *
                 for (int k = 0; k < wi; ++k) colp[k] = bstart[I] + k;
                 for (int k = 0; k < wj; ++k) colp[wi + k] = bstart[Jb] + k;
                 for (int k = 0; k < w; ++k) {
-                    JP[k] = (J && J[colp[k]] < 0) ? -1 : 1;
+                    JP[k] = Jc[colp[k]];
                     memcpy(GP + (size_t)k * m, Gr + (size_t)colp[k] * m, sizeof(real) * (size_t)m);
                 }
                 /* 1. pivot Gram */
@@ -442,9 +614,20 @@ static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *
                             need = 1;
                     }
                 if (bad || !need) continue;
-                /* 3. Cholesky A_P = R^T R (upper R, column-major w x w) */
-                int broke = 0;
-                for (int j = 0; j < w && !broke; ++j) {
+                /* 3. Cholesky A_P = R^T R (upper R, column-major w x w); with
+                 * sign pivoting P^T A_P P = R_S^T R_S (Alg. 3.3) and the inner
+                 * signs become those of the permuted positions */
+                int broke = 0, npos = 0;
+                for (int k = 0; k < w; ++k) { perm[k] = k; JS[k] = JP[k]; }
+                if (sign_pivot) {
+                    broke = sign_pivoted_cholesky(w, AP, JP, R, perm, &npos, SW, iw);
+                    if (broke) {
+                        for (int k = 0; k < w; ++k) perm[k] = k;
+                    } else {
+                        for (int k = 0; k < w; ++k) JS[k] = (k < npos) ? 1 : -1;
+                    }
+                }
+                for (int j = 0; j < w && !broke && !sign_pivot; ++j) {
                     for (int i = 0; i <= j; ++i) {
                         real sum = AP[(size_t)j * w + i];
                         for (int k = 0; k < i; ++k)
@@ -474,14 +657,23 @@ static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *
                 int inner = full_block ? max_inner : 1;
                 for (int it = 0; it < inner; ++it) {
                     long long r = inner_sweep(X, ldx, len, VP, w, istart, ipairs, isteps,
-                                              JP, (real)tol, &nclamp, &bad);
+                                              broke ? JP : JS, (real)tol, &nclamp, &bad);
                     prot += r;
                     if (bad || r == 0) break;
                 }
                 if (bad) break;
                 rot += prot;
                 /* 5. update G_P <- G_P V_P, V(:,P) <- V(:,P) V_P.  After a
-                 * breakdown G_P was transformed in place and is copied back. */
+                 * breakdown G_P was transformed in place and is copied back.
+                 * With sign pivoting V_P = P V': the permutation is applied
+                 * to the rows of the accumulated V' (Alg. 3.4), and column c
+                 * of the block takes the sign of position c. */
+                if (prot > 0 && sign_pivot && !broke) {
+                    memcpy(VQ, VP, sizeof(real) * (size_t)w * w);
+                    for (int c = 0; c < w; ++c)
+                        for (int r = 0; r < w; ++r) VP[(size_t)c * w + perm[r]] = VQ[(size_t)c * w + r];
+                    for (int c = 0; c < w; ++c) Jc[colp[c]] = JS[c];
+                }
                 if (prot > 0) {
                     if (broke) {
                         for (int c = 0; c < w; ++c)
@@ -515,7 +707,8 @@ static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *
         if (bad) { st = ORC_ENONFINITE; break; }
         if (rot == 0) { st = ORC_OK; break; }
     }
-    finalize(m, n, Gr, J, G, ldg, lambda);
+    finalize(m, n, Gr, Jc, G, ldg, lambda);
+    if (J_out) memcpy(J_out, Jc, (size_t)n);
     if (Vr)
         for (int i = 0; i < n; ++i)
             for (int k = 0; k < n; ++k) V[(size_t)i * ldv + k] = (double)Vr[(size_t)i * n + k];
@@ -524,6 +717,6 @@ static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *
 out:
     free(bstart); free(ostart); free(opairs); free(istart); free(ipairs);
     free(Gr); free(Vr); free(GP); free(VB); free(AP); free(R); free(VP); free(JP);
-    free(colp);
+    free(JS); free(Jc); free(colp); free(perm); free(iw); free(SW); free(VQ);
     return st;
 }

@@ -53,6 +53,15 @@ def lib():
                           ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _ip,
                           _llp, _llp]
             f.restype = ctypes.c_int
+            f = getattr(L, "orc_block_jevd_sp_" + s)
+            f.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _cp,
+                          ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _ip,
+                          _llp, _llp, _cp]
+            f.restype = ctypes.c_int
+            f = getattr(L, "orc_sp_cholesky_" + s)
+            f.argtypes = [ctypes.c_int, _dp, _cp, _dp, _ip, _ip]
+            f.restype = ctypes.c_int
             f = getattr(L, "orc_block_steps_" + s)
             f.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _cp, ctypes.c_double,
                           ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
@@ -137,8 +146,10 @@ def jevd(G, J=None, tol=None, ordering_kind=MODMODULUS, max_sweeps=50, want_v=Tr
 
 
 def block_jevd(G, J=None, tol=None, b=8, full_block=False, max_sweeps=50, max_inner=30,
-               want_v=True, V0=None, prec="d"):
-    """Block one-sided Jacobi (unpivoted Cholesky); see oracle/jacobi.c."""
+               want_v=True, V0=None, prec="d", sign_pivot=False):
+    """Block one-sided Jacobi; see oracle/jacobi.c.  sign_pivot selects the
+    sign-pivoted Cholesky of Alg. 3.3 (HBSC / HFSC); the result's .J then
+    holds the final column signs (the pivoting permutes them)."""
     G, m, n, Jb, V = _prep(G, J, want_v, V0)
     if tol is None:
         tol = n * np.finfo(np.float64).eps
@@ -146,12 +157,34 @@ def block_jevd(G, J=None, tol=None, b=8, full_block=False, max_sweeps=50, max_in
     sweeps = ctypes.c_int(0)
     rot = np.zeros(max(max_sweeps, 1), dtype=np.int64)
     nbr = ctypes.c_longlong(0)
-    f = getattr(lib(), "orc_block_jevd_" + prec)
-    st = f(m, n, _ptr(G), m, None if Jb is None else Jb.ctypes.data_as(_cp), float(tol),
-           b, 1 if full_block else 0, max_sweeps, max_inner, 1 if V0 is not None else 0,
-           _ptr(lam), None if V is None else _ptr(V), n, ctypes.byref(sweeps),
-           _ptr(rot, _llp), ctypes.byref(nbr))
-    return Result(st, G, lam, V, sweeps.value, rot[:sweeps.value].copy(), nbr.value)
+    Jp = None if Jb is None else Jb.ctypes.data_as(_cp)
+    args = [m, n, _ptr(G), m, Jp, float(tol), b, 1 if full_block else 0, max_sweeps, max_inner,
+            1 if V0 is not None else 0, _ptr(lam), None if V is None else _ptr(V), n,
+            ctypes.byref(sweeps), _ptr(rot, _llp), ctypes.byref(nbr)]
+    Jout = np.ones(n, dtype=np.int8)
+    if sign_pivot:
+        st = getattr(lib(), "orc_block_jevd_sp_" + prec)(*args, Jout.ctypes.data_as(_cp))
+    else:
+        st = getattr(lib(), "orc_block_jevd_" + prec)(*args)
+        if Jb is not None:
+            Jout = Jb.copy()
+    r = Result(st, G, lam, V, sweeps.value, rot[:sweeps.value].copy(), nbr.value)
+    r.J = Jout
+    return r
+
+
+def sp_cholesky(A, JP, prec="d"):
+    """Alg. 3.3 on one symmetric w x w Gram A with signs JP: returns
+    (status, R_S, perm, npos) with P^T A P = R_S^T R_S, P = I[:, perm]."""
+    A = np.array(A, dtype=np.float64, order="F", copy=True)
+    w = A.shape[0]
+    Jb = np.ascontiguousarray(np.asarray(JP).astype(np.int8))
+    RS = np.zeros((w, w), order="F")
+    perm = np.zeros(w, dtype=np.int32)
+    npos = ctypes.c_int(0)
+    st = getattr(lib(), "orc_sp_cholesky_" + prec)(w, _ptr(A), Jb.ctypes.data_as(_cp), _ptr(RS),
+                                                 _ptr(perm, _ip), ctypes.byref(npos))
+    return st, RS, perm, npos.value
 
 
 def block_steps(G, J=None, tol=None, b=32, full_block=False, max_inner=30, steps=1, prec="d"):

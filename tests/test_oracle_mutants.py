@@ -38,6 +38,16 @@ MUTANTS = {
     "block-update-transposed": ("jacobi.c",
                                 "acc = acc + GP[(size_t)k * m + r] * VP[(size_t)c * w + k];",
                                 "acc = acc + GP[(size_t)k * m + r] * VP[(size_t)k * w + c];"),
+    "sp-reversal-dropped": ("jacobi.c", "const int src = pp[nn - 1 - c];", "const int src = pp[c];"),
+    "sp-pivot-smallest": ("jacobi.c", "if (W[(size_t)i * k + i] > W[(size_t)t * k + t]) t = i;",
+                          "if (W[(size_t)i * k + i] < W[(size_t)t * k + t]) t = i;"),
+    "sp-schur-sign": ("jacobi.c",
+                      "sum = sum - RS[(size_t)(np + r) * w + k] * RS[(size_t)(np + c) * w + k];",
+                      "sum = sum + RS[(size_t)(np + r) * w + k] * RS[(size_t)(np + c) * w + k];"),
+    "sp-vp-rows-not-permuted": ("jacobi.c",
+                                "VP[(size_t)c * w + perm[r]] = VQ[(size_t)c * w + r];",
+                                "VP[(size_t)c * w + r] = VQ[(size_t)c * w + r];"),
+    "sp-signs-not-moved": ("jacobi.c", "for (int c = 0; c < w; ++c) Jc[colp[c]] = JS[c];", ""),
     "block-cholesky-term-dropped": ("jacobi.c",
                                     "sum = sum - R[(size_t)i * w + k] * R[(size_t)j * w + k];",
                                     "sum = sum - R[(size_t)i * w + k] * R[(size_t)i * w + k];"),
@@ -62,7 +72,8 @@ def test_pins_catch_planted_mistake(tmp_path, name):
     env = dict(os.environ, ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_ordering.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_signpivot.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "the pins did not notice the planted mistake %r" % name
     assert "failed" in r.stdout
