@@ -73,7 +73,19 @@ typedef struct {
     int max_inner;     /* full block: inner sweep limit per pivot, default 30 */
     int accumulate_v;  /* 0: V := I before the first sweep; 1: V holds a prior
                           transform on entry (resume from an earlier iterate) */
+    int pivot;         /* JEVD_PIVOT_*; default JEVD_PIVOT_NONE */
 } jevd_opts;
+
+/* Cholesky factorisation of the pivot Grams of the block variants. */
+enum {
+    JEVD_PIVOT_NONE = 0,  /* unpivoted (HB / HF, and the trigonometric block variants) */
+    JEVD_PIVOT_SIGN = 1   /* sign-pivoted, Alg. 3.3 (HBSC / HFSC; diagonal pivoting for J = I).
+                             Requires JEVD_VAR_BLOCK_ORIENTED or JEVD_VAR_FULL_BLOCK.  The
+                             pivoting permutes the columns of each transformed pivot block,
+                             positive signs first: on return column i of G, U, V carries the
+                             sign of lambda_i, which may differ from J[i], and V satisfies
+                             V^T J V = diag(sign(lambda)). */
+};
 
 /* Per-call diagnostics of the last jacobi_evd on a handle. */
 #define JEVD_INFO_MAX_SWEEPS 64

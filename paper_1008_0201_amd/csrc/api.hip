@@ -146,6 +146,7 @@ void fill_defaults(jevd_opts *o)
     o->max_sweeps = 50;
     o->max_inner = 30;
     o->accumulate_v = 0;
+    o->pivot = JEVD_PIVOT_NONE;
 }
 
 }  // namespace
@@ -203,6 +204,10 @@ int jevd_validate(int m, int n, int ldg, const signed char *J, double tol, const
         if (opts->accumulate_v != 0 && opts->accumulate_v != 1) return JEVD_EINVAL;
         if (opts->accumulate_v && !V) return JEVD_EINVAL;
         if (opts->block != 0 && !block_width_supported(opts->block)) return JEVD_EINVAL;
+        if (opts->pivot != JEVD_PIVOT_NONE && opts->pivot != JEVD_PIVOT_SIGN) return JEVD_EINVAL;
+        if (opts->pivot == JEVD_PIVOT_SIGN && opts->variant != JEVD_VAR_BLOCK_ORIENTED &&
+            opts->variant != JEVD_VAR_FULL_BLOCK)
+            return JEVD_EINVAL;
         if (opts->variant == JEVD_VAR_BLOCK_ORIENTED || opts->variant == JEVD_VAR_FULL_BLOCK) {
             const int b = opts->block ? opts->block : choose_block_width(m, n);
             if (!block_shape_supported(m, n, b)) return JEVD_EINVAL;
@@ -352,7 +357,7 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
     HIP_TRY(hipGetDevice(&dev));
     if (dev != h->device) return JEVD_EINVAL;  // handle belongs to another device
 
-    const signed char *dJ = nullptr;
+    signed char *dJ = nullptr;
     if (J) {
         st = grow_device(&h->dJ, &h->capJ, (size_t)n);
         if (st) return st;
@@ -375,7 +380,8 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
     } else {
         const int b = o.block ? o.block : choose_block_width(m, n);
         BlockRunArgs a{m, n, G, ldg, dJ, J, tol, variant == JEVD_VAR_FULL_BLOCK, b, o.max_sweeps,
-                       o.max_inner, V, ldv, h->stream, h->dctr, h->hctr, &h->timer};
+                       o.max_inner, V, ldv, o.pivot == JEVD_PIVOT_SIGN, h->stream, h->dctr,
+                       h->hctr, &h->timer};
         status = run_block(&h->blk, a, &sweeps_done);
         h->info.block = b;
         h->info.ordering = JEVD_ORD_MODMODULUS;

@@ -20,7 +20,7 @@ struct BlockRunArgs {
     int m, n;
     double *G;
     int ldg;
-    const signed char *dJ;   // device, may be null
+    signed char *dJ;         // device, may be null; rewritten by sign pivoting
     const signed char *hJ;   // host, may be null
     double tol;
     bool full_block;
@@ -28,6 +28,7 @@ struct BlockRunArgs {
     int max_sweeps, max_inner;
     double *V;
     int ldv;
+    bool sign_pivot;         // Alg. 3.3 in the pivot solve (HBSC / HFSC)
     hipStream_t stream;
     SweepCounters *dctr;  // max_sweeps slots, zeroed by run_block
     SweepCounters *hctr;  // pinned mirror

@@ -219,7 +219,7 @@ __device__ void inner_sweep_global(double *X, long ldx, int len, double *Y, long
 struct PivotSolveArgs {
     const double *partial;
     int nsplit;
-    const signed char *J;
+    signed char *J;  // device signs (null: J = I); rewritten by the sign pivoting
     const int2 *piv;
     int b;
     double tol;
@@ -232,6 +232,7 @@ struct PivotSolveArgs {
     double *G;
     int m;
     long ldg;
+    int sign_pivot;  // Alg. 3.3 instead of the unpivoted Cholesky
 };
 
 // LDS pitch of the factor R: one more than W (bank spread when the lanes of
@@ -259,8 +260,9 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     double *A = lds;                   // W x W column-major, pitch P: Gram, then R
     double *VP = lds + W * P;          // W x W column-major, pitch P (first: rows of R)
     double *red = VP + W * P;          // NW x 3 x NP partial dot products
-    __shared__ signed char JP[W];
-    __shared__ int s_need, s_bad, s_broke;
+    __shared__ signed char JP[W], JS[W];
+    __shared__ int s_piv[W], s_perm[W];
+    __shared__ int s_need, s_bad, s_broke, s_npos;
     __shared__ unsigned long long s_rot[NW], s_cl[NW];
     const int pv = blockIdx.x;
     const int2 IJ = a.piv[pv];
@@ -336,34 +338,122 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     // Cholesky A_P = R^T R, right-looking: step j writes row j of R
     // (r_jl = a_jl / r_jj) into the VP buffer, then, after a barrier,
     // subtracts r_ji r_jl from the trailing entries (i, l), j < i <= l.
-    for (int j = 0; j < W; ++j) {
-        const double d = A[j * P + j];
-        if (!(d > 0.0)) {
-            if (tid == 0) s_broke = 1;
-            break;  // d is the same for every thread: a uniform exit
+    if (!a.sign_pivot) {
+        for (int j = 0; j < W; ++j) {
+            const double d = A[j * P + j];
+            if (!(d > 0.0)) {
+                if (tid == 0) s_broke = 1;
+                break;  // d is the same for every thread: a uniform exit
+            }
+            const double rjj = sqrt(d);
+            for (int l = j + tid; l < W; l += kPivotThreads)
+                VP[l * P + j] = (l == j) ? rjj : A[l * P + j] / rjj;
+            __syncthreads();
+            const int nt = W - 1 - j;  // trailing order
+            for (int e = tid; e < nt * nt; e += kPivotThreads) {
+                const int i = j + 1 + e % nt, l = j + 1 + e / nt;
+                if (i <= l) A[l * P + i] -= VP[i * P + j] * VP[l * P + j];
+            }
+            __syncthreads();
         }
-        const double rjj = sqrt(d);
-        for (int l = j + tid; l < W; l += kPivotThreads)
-            VP[l * P + j] = (l == j) ? rjj : A[l * P + j] / rjj;
-        __syncthreads();
-        const int nt = W - 1 - j;  // trailing order
-        for (int e = tid; e < nt * nt; e += kPivotThreads) {
-            const int i = j + 1 + e % nt, l = j + 1 + e / nt;
-            if (i <= l) A[l * P + i] -= VP[i * P + j] * VP[l * P + j];
+    } else {
+        // Sign-pivoted Cholesky (Alg. 3.3) as one right-looking elimination
+        // over the positions of A_P reordered positive-first: eliminating
+        // positions 0..npos-1 with the pivot taken among them factors A_11
+        // with diagonal pivoting, forms R_12 = R_11^{-T} P_1^T A_12 in the
+        // same rows of R and leaves the Schur complement S = A_22 - R_12^T
+        // R_12 in the trailing block, which the remaining steps factor with
+        // pivots among positions npos..W-1 ((3.6), (3.7)).  piv maps a
+        // position to its column of A_P (rows and columns are not moved);
+        // both triangles of A are kept.  At step j the pivot is the largest
+        // remaining diagonal entry in the position's sign block (the first
+        // on ties); swapping positions j and t also swaps columns j and t of
+        // the rows of R formed so far.
+        if (wave == 0) {
+            const bool in = lane < W;
+            const bool isp = in && JP[lane] > 0;
+            const unsigned long long bp = __ballot(isp), bn = __ballot(in && !isp);
+            const int np = __popcll(bp);
+            const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            if (in) s_piv[isp ? __popcll(bp & below) : np + __popcll(bn & below)] = lane;
+            if (lane == 0) s_npos = np;
         }
         __syncthreads();
+        const int npos = s_npos;
+        for (int j = 0; j < W; ++j) {
+            const int hi = (j < npos) ? npos : W;
+            if (wave == 0) {
+                const int i = j + lane;
+                double v = -1.0;
+                int idx = W;
+                if (i < hi) {
+                    v = A[s_piv[i] * P + s_piv[i]];
+                    idx = i;
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ov = __shfl_xor(v, off);
+                    const int oi = __shfl_xor(idx, off);
+                    if (ov > v || (ov == v && oi < idx)) {
+                        v = ov;
+                        idx = oi;
+                    }
+                }
+                const int t = idx;   // the same in every lane
+                if (t != j && t < W) {
+                    if (lane < j) {
+                        const double x = VP[j * P + lane];
+                        VP[j * P + lane] = VP[t * P + lane];
+                        VP[t * P + lane] = x;
+                    }
+                    if (lane == 0) {
+                        const int x = s_piv[j];
+                        s_piv[j] = s_piv[t];
+                        s_piv[t] = x;
+                    }
+                }
+            }
+            __syncthreads();
+            const int pj = s_piv[j];
+            const double d = A[pj * P + pj];
+            if (!(d > 0.0)) {
+                if (tid == 0) s_broke = 1;
+                break;  // uniform exit
+            }
+            const double rjj = sqrt(d);
+            for (int l = j + tid; l < W; l += kPivotThreads)
+                VP[l * P + j] = (l == j) ? rjj : A[s_piv[l] * P + pj] / rjj;
+            __syncthreads();
+            const int nt = W - 1 - j;
+            for (int e = tid; e < nt * nt; e += kPivotThreads) {
+                const int i = j + 1 + e % nt, l = j + 1 + e / nt;
+                A[s_piv[l] * P + s_piv[i]] -= VP[i * P + j] * VP[l * P + j];
+            }
+            __syncthreads();
+        }
     }
     const bool broke = s_broke != 0;
     unsigned long long rot = 0, ncl = 0;
     int bad = 0;
     if (!broke) {
-        // R (upper) from the VP buffer into A
+        // R (upper) from the VP buffer into A; with sign pivoting the
+        // columns of the negative block are reversed (Alg. 3.3) and
+        // position c takes the sign +1 for c < npos, else -1
+        const int npos = a.sign_pivot ? s_npos : W;
         for (int e = tid; e < W * W; e += kPivotThreads) {
             const int r = e % W, c = e / W;
-            A[c * P + r] = (r <= c) ? VP[c * P + r] : 0.0;
+            const int src = (c < npos) ? c : npos + (W - 1 - c);
+            A[c * P + r] = (r <= src) ? VP[src * P + r] : 0.0;
+        }
+        if (a.sign_pivot && tid < W) {
+            const int src = (tid < npos) ? tid : npos + (W - 1 - tid);
+            s_perm[tid] = s_piv[src];
+            JS[tid] = (tid < npos) ? (signed char)1 : (signed char)-1;
         }
         __syncthreads();
     }
+    // signs of the inner transforms: of the permuted positions after a
+    // sign-pivoted factorisation, else of the pivot's own columns
+    const signed char *JI = (a.sign_pivot && !broke) ? JS : JP;
     for (int e = tid; e < W * W; e += kPivotThreads) {   // V_P := I
         const int r = e % W, c = e / W;
         VP[c * P + r] = (r == c) ? 1.0 : 0.0;
@@ -423,7 +513,7 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
                     act = false;
                 }
                 act = act && needs_rotation(app, aqq, apq, a.tol);
-                const bool same = act ? (JP[pq.x] == JP[pq.y]) : true;
+                const bool same = act ? (JI[pq.x] == JI[pq.y]) : true;
                 double c = 1.0, sn = 0.0;
                 if (act && transform_params(app, aqq, apq, same, c, sn) && wave == 0) ++ncl;
                 if (act) {
@@ -485,11 +575,16 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
         a.flag[pv] = (tot > 0 && !s_bad) ? (broke ? 2 : 1) : 0;
     }
     if (tot > 0) {
+        // V_P row-major; after a sign-pivoted factorisation V_P = P V' (the
+        // permutation applied to the rows of V', Alg. 3.4), and column c of
+        // the pivot block takes the sign of position c
+        const bool sp = a.sign_pivot && !broke;
         double *out = a.vpt + (size_t)pv * W * W;
         for (int e = tid; e < W * W; e += kPivotThreads) {
             const int r = e / W, c = e % W;
-            out[e] = VP[c * P + r];
+            out[(sp ? s_perm[r] : r) * W + c] = VP[c * P + r];
         }
+        if (sp && a.J && !s_bad && tid < W) a.J[pivot_col(tid, IJ, b)] = JS[tid];
     }
 }
 
@@ -684,6 +779,7 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     p.G = a.G;
     p.m = a.m;
     p.ldg = a.ldg;
+    p.sign_pivot = a.sign_pivot ? 1 : 0;
     if ((e = a.timer->begin(st, JEVD_K_PIVOT_SOLVE)) != hipSuccess) return e;
     k_pivot_solve<W><<<npiv, kPivotThreads, pivot_lds_bytes(W), st>>>(p);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libjevd.so")
 JEVD_OK, JEVD_EINVAL, JEVD_ENONFINITE, JEVD_ENOCONV, JEVD_EHIP, JEVD_ENOMEM = 0, -1, -2, -3, -4, -5
 ORD_ROWCYCLIC, ORD_MODULUS, ORD_MODMODULUS = 0, 1, 2
 VAR_POINTWISE, VAR_BLOCK_ORIENTED, VAR_FULL_BLOCK, VAR_AUTO = 0, 1, 2, 3
+PIVOT_NONE, PIVOT_SIGN = 0, 1
 INFO_MAX_SWEEPS = 64
 
 EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "jevd_validate",
@@ -26,7 +27,7 @@ K_PAIR_STEP, K_GRAM, K_PIVOT_SOLVE, K_UPDATE = 0, 1, 2, 3
 class jevd_opts(ctypes.Structure):
     _fields_ = [("ordering", ctypes.c_int), ("variant", ctypes.c_int), ("block", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("max_inner", ctypes.c_int),
-                ("accumulate_v", ctypes.c_int)]
+                ("accumulate_v", ctypes.c_int), ("pivot", ctypes.c_int)]
 
 
 class jevd_info(ctypes.Structure):
@@ -267,7 +268,8 @@ class Solver:
             pass
 
     def evd(self, G, J=None, tol=0.0, ordering=ORD_MODMODULUS, variant=VAR_AUTO, block=0,
-            max_sweeps=50, max_inner=30, want_U=True, want_V=True, V0=None, check=True):
+            max_sweeps=50, max_inner=30, want_U=True, want_V=True, V0=None, check=True,
+            pivot=PIVOT_NONE):
         """Solve in place on the device tensor G (float64, column-major: pass
         a tensor whose .T is contiguous, or any (m, n) tensor with stride
         (1, ldg)).  Returns (lam, U, V, sweeps, status)."""
@@ -285,6 +287,7 @@ class Solver:
         o = jevd_default_opts()
         o.ordering, o.variant, o.block = ordering, variant, block
         o.max_sweeps, o.max_inner = max_sweeps, max_inner
+        o.pivot = pivot
         if V0 is not None:
             V = V0
             o.accumulate_v = 1
