@@ -74,7 +74,21 @@ typedef struct {
     int accumulate_v;  /* 0: V := I before the first sweep; 1: V holds a prior
                           transform on entry (resume from an earlier iterate) */
     int pivot;         /* JEVD_PIVOT_*; default JEVD_PIVOT_NONE */
+    int precision;     /* JEVD_PREC_*; default JEVD_PREC_FP64 */
 } jevd_opts;
+
+/* Arithmetic of the block sweeps. */
+enum {
+    JEVD_PREC_FP64 = 0,   /* every sweep in FP64 */
+    JEVD_PREC_MIXED = 1   /* block sweeps on an FP32 copy of G (FP32 MFMA Gram and update;
+                             Cholesky, rotation angles and the skip test in FP64) at the
+                             threshold tol_low = max(tol, 8 sqrt(m) 2^-24), until a sweep
+                             rotates nothing there or max_sweeps; then the FP32 transform is
+                             made orthogonal in FP64 (Newton-Schulz), G <- G V0 in FP64, and
+                             FP64 block sweeps finish at tol.  Requires a block variant,
+                             J = I and accumulate_v = 0; V may be NULL (a work array is used).
+                             jevd_info.sweeps_low counts the FP32 sweeps; sweeps the FP64 ones. */
+};
 
 /* Cholesky factorisation of the pivot Grams of the block variants. */
 enum {
@@ -109,6 +123,7 @@ typedef struct {
      * durations of each kernel class and the number of its launches. */
     double kernel_ms[JEVD_K_CLASSES];
     long long kernel_launches[JEVD_K_CLASSES];
+    int sweeps_low;    /* JEVD_PREC_MIXED: FP32 sweeps before the FP64 ones */
 } jevd_info;
 
 /* Fills *o with the defaults listed above.  Never fails for a non-NULL o. */

@@ -72,6 +72,8 @@ struct jevd_handle_s {
     KernelTimer timer;
     jevd_info info;
 
+    double *vtmp = nullptr;  // V work array of the mixed path when V is not wanted
+    size_t capVtmp = 0;
     // adjoint work arrays: K, W, M' (n x n) and T (m x n) per instance
     double *adjK = nullptr, *adjW = nullptr, *adjM = nullptr, *adjT = nullptr;
     size_t capAdjK = 0, capAdjW = 0, capAdjM = 0, capAdjT = 0;
@@ -147,6 +149,7 @@ void fill_defaults(jevd_opts *o)
     o->max_inner = 30;
     o->accumulate_v = 0;
     o->pivot = JEVD_PIVOT_NONE;
+    o->precision = JEVD_PREC_FP64;
 }
 
 }  // namespace
@@ -208,6 +211,15 @@ int jevd_validate(int m, int n, int ldg, const signed char *J, double tol, const
         if (opts->pivot == JEVD_PIVOT_SIGN && opts->variant != JEVD_VAR_BLOCK_ORIENTED &&
             opts->variant != JEVD_VAR_FULL_BLOCK)
             return JEVD_EINVAL;
+        if (opts->precision != JEVD_PREC_FP64 && opts->precision != JEVD_PREC_MIXED) return JEVD_EINVAL;
+        if (opts->precision == JEVD_PREC_MIXED) {
+            if (opts->variant != JEVD_VAR_BLOCK_ORIENTED && opts->variant != JEVD_VAR_FULL_BLOCK)
+                return JEVD_EINVAL;
+            if (opts->accumulate_v) return JEVD_EINVAL;
+            if (J)
+                for (int i = 0; i < n; ++i)
+                    if (J[i] != 1) return JEVD_EINVAL;
+        }
         if (opts->variant == JEVD_VAR_BLOCK_ORIENTED || opts->variant == JEVD_VAR_FULL_BLOCK) {
             const int b = opts->block ? opts->block : choose_block_width(m, n);
             if (!block_shape_supported(m, n, b)) return JEVD_EINVAL;
@@ -253,6 +265,7 @@ int jevd_destroy(jevd_handle_t h)
     if (h->dpairs) (void)hipFree(h->dpairs);
     if (h->dstep) (void)hipFree(h->dstep);
     if (h->dslots) (void)hipFree(h->dslots);
+    if (h->vtmp) (void)hipFree(h->vtmp);
     if (h->adjK) (void)hipFree(h->adjK);
     if (h->adjW) (void)hipFree(h->adjW);
     if (h->adjM) (void)hipFree(h->adjM);
@@ -382,7 +395,19 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
         BlockRunArgs a{m, n, G, ldg, dJ, J, tol, variant == JEVD_VAR_FULL_BLOCK, b, o.max_sweeps,
                        o.max_inner, V, ldv, o.pivot == JEVD_PIVOT_SIGN, h->stream, h->dctr,
                        h->hctr, &h->timer};
-        status = run_block(&h->blk, a, &sweeps_done);
+        if (o.precision == JEVD_PREC_MIXED) {
+            if (!V) {
+                st = grow_device(&h->vtmp, &h->capVtmp, (size_t)n * n);
+                if (st) return st;
+                a.V = h->vtmp;
+                a.ldv = n;
+            }
+            int low = 0;
+            status = run_block_mixed(&h->blk, a, o.max_sweeps, &low, &sweeps_done);
+            h->info.sweeps_low = low;
+        } else {
+            status = run_block(&h->blk, a, &sweeps_done);
+        }
         h->info.block = b;
         h->info.ordering = JEVD_ORD_MODMODULUS;
     }

@@ -14,6 +14,10 @@ struct BlockWorkspace {
     int *flags = nullptr;       // per pivot: 1 if its transform must be applied
     size_t capPartial = 0, capVp = 0, capFlags = 0;
     void *tables = nullptr;     // block and inner orderings (device copies)
+    // mixed precision: FP32 iterate and transform, FP64 work arrays
+    float *g32 = nullptr, *v32 = nullptr;
+    double *t64 = nullptr, *w64 = nullptr;
+    size_t capG32 = 0, capV32 = 0, capT64 = 0, capW64 = 0;
 };
 
 struct BlockRunArgs {
@@ -40,6 +44,10 @@ bool block_shape_supported(int m, int n, int b);
 int choose_block_width(int m, int n);
 int auto_variant(int m, int n);
 int run_block(BlockWorkspace *ws, const BlockRunArgs &a, int *sweeps_done);
+// FP32-MFMA block sweeps, V0 made orthogonal in FP64, G <- G V0, then FP64
+// block sweeps (a.V required; J = I).
+int run_block_mixed(BlockWorkspace *ws, const BlockRunArgs &a, int max_sweeps_low, int *sweeps_low,
+                    int *sweeps_done);
 void block_workspace_free(BlockWorkspace *ws);
 
 }  // namespace jevd

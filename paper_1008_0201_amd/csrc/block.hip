@@ -24,6 +24,7 @@
 
 #include "../../include/jevd.h"
 #include "block.h"
+#include "gemm.h"
 #include "device_math.h"
 #include "ordering.h"
 
@@ -39,6 +40,26 @@ __device__ __forceinline__ d4 mfma16x16x4(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// The same product for FP32 operands (v_mfma_f32_16x16x4f32): the operand
+// layout is that of the FP64 instruction, but element r of the result in
+// lane l is D[4 (l / 16) + r][l % 16].
+typedef float f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Accumulator type and result row of the 16 x 16 x 4 product per element type.
+template <class T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef d4 acc;
+    __device__ static int row(int lane, int r) { return lane / 16 + 4 * r; }
+};
+template <> struct Mfma<float> {
+    typedef f4 acc;
+    __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
+
 // Global column of pivot-local column k of the block pair (I, J).
 __device__ __forceinline__ int pivot_col(int k, int2 IJ, int b)
 {
@@ -49,8 +70,8 @@ __device__ __forceinline__ int pivot_col(int k, int2 IJ, int b)
 // 32-row slabs of G_P are staged transposed in LDS (row pitch W+1), double
 // buffered: the loads of slab s+1 are in flight in registers while the
 // MFMAs of slab s run, with one barrier per slab.
-template <int W>
-__global__ __launch_bounds__(256) void k_gram(const double *__restrict__ G, int m, long ldg, int b,
+template <int W, class T>
+__global__ __launch_bounds__(256) void k_gram(const T *__restrict__ G, int m, long ldg, int b,
                                               const int2 *__restrict__ piv, int rows_per_split,
                                               double *__restrict__ partial)
 {
@@ -60,7 +81,7 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ G, int 
     constexpr int NUP = NT * (NT + 1) / 2;    // upper tiles, diagonal included
     constexpr int TPW = (NUP + 3) / 4;        // tiles per wavefront
     constexpr int EPT = KR * W / 256;         // staged elements per thread
-    __shared__ double st[2][KR * LDC];        // st[buf][kr][c] = G_P[r0 + kr][c]
+    __shared__ T st[2][KR * LDC];             // st[buf][kr][c] = G_P[r0 + kr][c]
     const int pv = blockIdx.x, split = blockIdx.y;
     const int2 IJ = piv[pv];
     const int r_begin = split * rows_per_split;
@@ -81,12 +102,12 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ G, int 
             tj[q] = it + t;
         }
     }
-    d4 acc[TPW];
+    typename Mfma<T>::acc acc[TPW];
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < TPW; ++q) acc[q] = typename Mfma<T>::acc{0, 0, 0, 0};
 
     // element u of this thread's slab share: row kr = e % KR, column c = e / KR
-    const double *colp[EPT];
+    const T *colp[EPT];
     int kr_of[EPT], c_of[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
@@ -95,11 +116,11 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ G, int 
         c_of[u] = e / KR;
         colp[u] = G + (size_t)pivot_col(c_of[u], IJ, b) * ldg;
     }
-    double reg[EPT];
+    T reg[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
         const int r = r_begin + kr_of[u];
-        reg[u] = (r < r_end) ? colp[u][r] : 0.0;
+        reg[u] = (r < r_end) ? colp[u][r] : T(0);
     }
     int buf = 0;
     for (int r0 = r_begin; r0 < r_end; r0 += KR) {
@@ -111,17 +132,17 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ G, int 
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
                 const int r = r1 + kr_of[u];
-                reg[u] = (r < r_end) ? colp[u][r] : 0.0;
+                reg[u] = (r < r_end) ? colp[u][r] : T(0);
             }
         }
 #pragma unroll
         for (int k = 0; k < KR; k += 4) {
-            const double *row = st[buf] + (k + lane / 16) * LDC + (lane % 16);
+            const T *row = st[buf] + (k + lane / 16) * LDC + (lane % 16);
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
                 if (ti[q] >= 0) {
-                    const double x = row[ti[q] * 16];
-                    const double y = row[tj[q] * 16];
+                    const T x = row[ti[q] * 16];
+                    const T y = row[tj[q] * 16];
                     acc[q] = mfma16x16x4(x, y, acc[q]);
                 }
             }
@@ -134,8 +155,8 @@ __global__ __launch_bounds__(256) void k_gram(const double *__restrict__ G, int 
         if (ti[q] < 0) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = ti[q] * 16 + lane / 16 + 4 * r, col = tj[q] * 16 + lane % 16;
-            out[(size_t)col * W + row] = acc[q][r];
+            const int row = ti[q] * 16 + Mfma<T>::row(lane, r), col = tj[q] * 16 + lane % 16;
+            out[(size_t)col * W + row] = (double)acc[q][r];
         }
     }
 }
@@ -432,6 +453,15 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
         }
     }
     const bool broke = s_broke != 0;
+    if (broke && !a.G) {
+        // no FP64 copy of G to transform in place (the FP32 sweeps): the
+        // pivot is left to the FP64 sweeps that follow
+        if (tid == 0) {
+            atomicAdd(&a.ctr->breakdowns, 1ull);
+            a.flag[pv] = 0;
+        }
+        return;
+    }
     unsigned long long rot = 0, ncl = 0;
     int bad = 0;
     if (!broke) {
@@ -594,9 +624,9 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
 // flight while the MFMAs of tile t run.
 constexpr int kUpdateTiles = 4;
 
-template <int W>
-__global__ __launch_bounds__(256) void k_update(double *__restrict__ G, int m, long ldg,
-                                                double *__restrict__ V, int nv, long ldv, int b,
+template <int W, class T>
+__global__ __launch_bounds__(256) void k_update(T *__restrict__ G, int m, long ldg,
+                                                T *__restrict__ V, int nv, long ldv, int b,
                                                 const int2 *__restrict__ piv,
                                                 const double *__restrict__ vpt,
                                                 const int *__restrict__ flag, int groups_g)
@@ -606,12 +636,12 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ G, int m, l
     // V_P row-major with a row pitch of W + 16 doubles: the four 16-lane row
     // groups of a fragment read then cover all 64 LDS banks in two cycles
     constexpr int SP = W + 16;
-    __shared__ double S[W * SP];
+    __shared__ T S[W * SP];
     const int pv = blockIdx.y;
     const bool is_v = (int)blockIdx.x >= groups_g;
     const int f = flag[pv];
     if (!(f == 1 || (is_v && f == 2))) return;   // flag 2: G_P already transformed
-    double *X = is_v ? V : G;
+    T *X = is_v ? V : G;
     const long ld = is_v ? ldv : ldg;
     const int rows = is_v ? nv : m;
     const int2 IJ = piv[pv];
@@ -620,45 +650,52 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ G, int m, l
     const int row0 = group * 64 * kUpdateTiles + wave * 16 + lane % 16;
 
     const double *src = vpt + (size_t)pv * W * W;
-    for (int e = threadIdx.x; e < W * W; e += 256) S[(e / W) * SP + (e % W)] = src[e];
+    for (int e = threadIdx.x; e < W * W; e += 256) S[(e / W) * SP + (e % W)] = (T)src[e];
     // Pivot columns 4g .. 4g+3 lie in one block (b is a multiple of 4), so
     // the column of lane l in k-step ks is the wave-uniform pivot_col(4 ks)
     // plus l / 16: wave-uniform column bases and one 32-bit per-lane offset.
     const unsigned lane_off = (unsigned)(lane / 16) * (unsigned)ld;
-    double bf[KS];
+    T bf[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        const double *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
-        bf[ks] = (row0 < rows) ? cb[lane_off + (unsigned)row0] : 0.0;
+        const T *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
+        bf[ks] = (row0 < rows) ? cb[lane_off + (unsigned)row0] : T(0);
     }
     __syncthreads();
     for (int t = 0; t < kUpdateTiles; ++t) {
         const int row = row0 + t * 64;
         if (row - lane % 16 >= rows) break;   // the same for all lanes of the wavefront
-        double nb[KS];
+        T nb[KS];
         const int rn = row + 64;
         const bool more = t + 1 < kUpdateTiles && rn < rows;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const double *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
-            nb[ks] = more ? cb[lane_off + (unsigned)rn] : 0.0;
+            const T *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
+            nb[ks] = more ? cb[lane_off + (unsigned)rn] : T(0);
         }
-        d4 acc[NT];
+        typename Mfma<T>::acc acc[NT];
 #pragma unroll
-        for (int q = 0; q < NT; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int q = 0; q < NT; ++q) acc[q] = typename Mfma<T>::acc{0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const double *srow = S + (4 * ks + lane / 16) * SP + (lane % 16);
+            const T *srow = S + (4 * ks + lane / 16) * SP + (lane % 16);
 #pragma unroll
             for (int q = 0; q < NT; ++q) acc[q] = mfma16x16x4(srow[q * 16], bf[ks], acc[q]);
         }
         if (row < rows) {
+            // element r of tile q is column q 16 + Mfma<T>::row(lane, r) of the
+            // block pair (a 16-column tile lies inside one block: 16 | b)
 #pragma unroll
             for (int q = 0; q < NT; ++q)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    double *cb = X + (size_t)pivot_col(q * 16 + 4 * r, IJ, b) * ld;
-                    cb[lane_off + (unsigned)row] = acc[q][r];
+                    if constexpr (sizeof(T) == 8) {
+                        T *cb = X + (size_t)pivot_col(q * 16 + 4 * r, IJ, b) * ld;
+                        cb[lane_off + (unsigned)row] = acc[q][r];
+                    } else {
+                        T *cb = X + (size_t)(pivot_col(q * 16, IJ, b) + Mfma<T>::row(lane, r)) * ld;
+                        cb[(unsigned)row] = acc[q][r];
+                    }
                 }
         }
 #pragma unroll
@@ -748,18 +785,23 @@ static size_t pivot_lds_bytes(int W)
     return (2 * (size_t)W * (W + 1) + 3 * (size_t)(kPivotThreads / 64) * (W / 2)) * sizeof(double);
 }
 
-// One outer step: Gram, pivot solve, update of G and V (one launch).
-template <int W>
+// One outer step: Gram, pivot solve, update of G and V (one launch each) on
+// the iterate G (and V) of element type T.  The pivot solve always runs in
+// FP64 on the Gram partials; tol is the step's rotation threshold.  For
+// T = float there is no FP64 copy of G for the in-place breakdown path, so a
+// pivot whose Cholesky breaks down is left for the FP64 sweeps.
+template <int W, class T>
 static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTables *t, int k,
-                              int nsplit, int rows_per_split, SweepCounters *ctr)
+                              int nsplit, int rows_per_split, SweepCounters *ctr, T *G, long ldg,
+                              T *V, long ldv, double tol)
 {
     const int npiv = t->N / 2;
     const int2 *piv = t->d_outer + t->outer_start[k];
     hipStream_t st = a.stream;
     hipError_t e;
     if ((e = a.timer->begin(st, JEVD_K_GRAM)) != hipSuccess) return e;
-    k_gram<W><<<dim3(npiv, nsplit), 256, 0, st>>>(a.G, a.m, (long)a.ldg, a.b, piv, rows_per_split,
-                                                   ws->partial);
+    k_gram<W, T><<<dim3(npiv, nsplit), 256, 0, st>>>(G, a.m, ldg, a.b, piv, rows_per_split,
+                                                      ws->partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = a.timer->end(st)) != hipSuccess) return e;
 
@@ -769,16 +811,16 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     p.J = a.dJ;
     p.piv = piv;
     p.b = a.b;
-    p.tol = a.tol;
+    p.tol = tol;
     p.all_pairs = (a.full_block || k == 0) ? 1 : 0;
     p.full_block = a.full_block ? 1 : 0;
     p.max_inner = a.max_inner;
     p.vpt = ws->vp;
     p.flag = ws->flags;
     p.ctr = ctr;
-    p.G = a.G;
+    p.G = (sizeof(T) == sizeof(double)) ? (double *)G : nullptr;
     p.m = a.m;
-    p.ldg = a.ldg;
+    p.ldg = ldg;
     p.sign_pivot = a.sign_pivot ? 1 : 0;
     if ((e = a.timer->begin(st, JEVD_K_PIVOT_SOLVE)) != hipSuccess) return e;
     k_pivot_solve<W><<<npiv, kPivotThreads, pivot_lds_bytes(W), st>>>(p);
@@ -787,24 +829,23 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
 
     const int rows_per_group = 64 * kUpdateTiles;
     const int groups_g = (a.m + rows_per_group - 1) / rows_per_group;
-    const int groups_v = a.V ? (a.n + rows_per_group - 1) / rows_per_group : 0;
+    const int groups_v = V ? (a.n + rows_per_group - 1) / rows_per_group : 0;
     if ((e = a.timer->begin(st, JEVD_K_UPDATE)) != hipSuccess) return e;
-    k_update<W><<<dim3(groups_g + groups_v, npiv), 256, 0, st>>>(a.G, a.m, (long)a.ldg, a.V, a.n,
-                                                                 (long)a.ldv, a.b, piv, ws->vp,
-                                                                 ws->flags, groups_g);
+    k_update<W, T><<<dim3(groups_g + groups_v, npiv), 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, a.b,
+                                                                    piv, ws->vp, ws->flags,
+                                                                    groups_g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return a.timer->end(st);
 }
 
-int run_block(BlockWorkspace *ws, const BlockRunArgs &a, int *sweeps_done)
+// Row split of the pivot Grams (about 1024 workgroups per step) and the
+// step workspaces; sets the pivot solve's LDS limit.
+static int prepare_steps(BlockWorkspace *ws, const BlockRunArgs &a, int *nsplit_out,
+                         int *rows_per_split_out)
 {
-    *sweeps_done = 0;
-    if (!block_shape_supported(a.m, a.n, a.b)) return JEVD_EINVAL;
     const int b = a.b, W = 2 * b, N = a.n / b, npiv = N / 2;
     int rc = prepare_tables(ws, N, b, a.stream);
     if (rc) return rc;
-    BlockTables *t = tables_of(ws);
-    // split the rows of each Gram so that a step has about 1024 workgroups
     int nsplit = 1024 / npiv;
     if (nsplit < 1) nsplit = 1;
     int maxsplit = (a.m + 255) / 256;
@@ -822,22 +863,155 @@ int run_block(BlockWorkspace *ws, const BlockRunArgs &a, int *sweeps_done)
         HIP_TRY(hipFuncSetAttribute((const void *)k_pivot_solve<64>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)pivot_lds_bytes(64)));
-    HIP_TRY(hipMemsetAsync(a.dctr, 0, sizeof(SweepCounters) * a.max_sweeps, a.stream));
-    for (int s = 0; s < a.max_sweeps; ++s) {
+    *nsplit_out = nsplit;
+    *rows_per_split_out = rows_per_split;
+    return JEVD_OK;
+}
+
+// Block sweeps over the iterate (G, V) of type T until a sweep rotates
+// nothing (at tol) or max_sweeps; counters in ctr[0 .. max_sweeps).  With
+// stop_on_stall the sweeps also end (JEVD_OK) once a sweep after the third
+// rotates at least as often as the one before: the rounding of the low-
+// precision iterate, not the ordering, then decides the rotations.
+template <class T>
+static int block_sweeps(BlockWorkspace *ws, const BlockRunArgs &a, T *G, long ldg, T *V, long ldv,
+                        double tol, int max_sweeps, SweepCounters *dctr, SweepCounters *hctr,
+                        int *sweeps_done, bool stop_on_stall = false)
+{
+    *sweeps_done = 0;
+    int nsplit = 0, rows_per_split = 0;
+    int rc = prepare_steps(ws, a, &nsplit, &rows_per_split);
+    if (rc) return rc;
+    BlockTables *t = tables_of(ws);
+    const int N = a.n / a.b;
+    HIP_TRY(hipMemsetAsync(dctr, 0, sizeof(SweepCounters) * max_sweeps, a.stream));
+    for (int s = 0; s < max_sweeps; ++s) {
         for (int k = 0; k < N; ++k) {
-            hipError_t e = (W == 32) ? launch_step<32>(ws, a, t, k, nsplit, rows_per_split, a.dctr + s)
-                                     : launch_step<64>(ws, a, t, k, nsplit, rows_per_split, a.dctr + s);
+            hipError_t e = (a.b == 16)
+                ? launch_step<32, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol)
+                : launch_step<64, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol);
             HIP_TRY(e);
         }
-        HIP_TRY(hipMemcpyAsync(a.hctr + s, a.dctr + s, sizeof(SweepCounters), hipMemcpyDeviceToHost,
+        HIP_TRY(hipMemcpyAsync(hctr + s, dctr + s, sizeof(SweepCounters), hipMemcpyDeviceToHost,
                                a.stream));
         HIP_TRY(hipStreamSynchronize(a.stream));
         HIP_TRY(a.timer->collect());
         *sweeps_done = s + 1;
-        if (a.hctr[s].nonfinite) return JEVD_ENONFINITE;
-        if (a.hctr[s].rotations == 0) return JEVD_OK;
+        if (hctr[s].nonfinite) return JEVD_ENONFINITE;
+        if (hctr[s].rotations == 0) return JEVD_OK;
+        if (stop_on_stall && s >= 3 && hctr[s].rotations >= hctr[s - 1].rotations) return JEVD_OK;
     }
     return JEVD_ENOCONV;
+}
+
+int run_block(BlockWorkspace *ws, const BlockRunArgs &a, int *sweeps_done)
+{
+    *sweeps_done = 0;
+    if (!block_shape_supported(a.m, a.n, a.b)) return JEVD_EINVAL;
+    return block_sweeps<double>(ws, a, a.G, a.ldg, a.V, a.ldv, a.tol, a.max_sweeps, a.dctr, a.hctr,
+                                sweeps_done);
+}
+
+// ------------------------------------------------------- mixed precision
+__global__ void k_to_f32(const double *__restrict__ X, long ldx, float *__restrict__ Y, long ldy,
+                         int rows, int cols)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)rows * cols) return;
+    const int r = (int)(e % rows), c = (int)(e / rows);
+    Y[(size_t)c * ldy + r] = (float)X[(size_t)c * ldx + r];
+}
+
+__global__ void k_to_f64(const float *__restrict__ X, long ldx, double *__restrict__ Y, long ldy,
+                         int rows, int cols)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)rows * cols) return;
+    const int r = (int)(e % rows), c = (int)(e / rows);
+    Y[(size_t)c * ldy + r] = (double)X[(size_t)c * ldx + r];
+}
+
+__global__ void k_identity_f32(float *__restrict__ X, long ldx, int n)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * n) return;
+    const int r = (int)(e % n), c = (int)(e / n);
+    X[(size_t)c * ldx + r] = (r == c) ? 1.0f : 0.0f;
+}
+
+// T <- (3 I - T) / 2 (n x n, ld n)
+__global__ void k_newton_schulz(double *__restrict__ T, int n)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * n) return;
+    const int r = (int)(e % n), c = (int)(e / n);
+    T[e] = ((r == c) ? 1.5 : 0.0) - 0.5 * T[e];
+}
+
+static unsigned blocks_for(long count) { return (unsigned)((count + 255) / 256); }
+
+static void gemm1(bool ta, bool tb, int M, int N, int K, const double *A, int lda, const double *B,
+                  int ldb, double *D, int ldd, hipStream_t st)
+{
+    GemmArgs g{};
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.A = A;
+    g.lda = lda;
+    g.B = B;
+    g.ldb = ldb;
+    g.D = D;
+    g.ldd = ldd;
+    launch_gemm(ta, tb, g, 1, st);
+}
+
+int run_block_mixed(BlockWorkspace *ws, const BlockRunArgs &a, int max_sweeps_low, int *sweeps_low,
+                    int *sweeps_done)
+{
+    *sweeps_low = 0;
+    *sweeps_done = 0;
+    if (!block_shape_supported(a.m, a.n, a.b) || !a.V) return JEVD_EINVAL;
+    const int m = a.m, n = a.n;
+    hipStream_t st = a.stream;
+    int rc;
+    if ((rc = grow(&ws->g32, &ws->capG32, (size_t)m * n))) return rc;
+    if ((rc = grow(&ws->v32, &ws->capV32, (size_t)n * n))) return rc;
+    if ((rc = grow(&ws->t64, &ws->capT64, (size_t)n * n))) return rc;
+    // w64: two n x n iterates of the orthogonalisation, later G V0 (m x n)
+    if ((rc = grow(&ws->w64, &ws->capW64, std::max((size_t)m * n, 2 * (size_t)n * n)))) return rc;
+    // 1. FP32 copy of G, V32 = I; FP32 sweeps at the threshold the FP32
+    //    Grams can resolve
+    k_to_f32<<<blocks_for((long)m * n), 256, 0, st>>>(a.G, a.ldg, ws->g32, m, m, n);
+    k_identity_f32<<<blocks_for((long)n * n), 256, 0, st>>>(ws->v32, n, n);
+    HIP_TRY(hipGetLastError());
+    const double tol_low = std::max(a.tol, 8.0 * std::sqrt((double)m) * 0x1p-24);
+    int s32 = 0;
+    rc = block_sweeps<float>(ws, a, ws->g32, m, ws->v32, n, tol_low, max_sweeps_low, a.dctr, a.hctr,
+                             &s32, true);
+    *sweeps_low = s32;
+    if (rc != JEVD_OK && rc != JEVD_ENOCONV) return rc;
+    // 2. V0 in FP64, made orthogonal to working precision by two Newton-
+    //    Schulz steps V <- V (3 I - V^T V) / 2 (quadratic convergence to the
+    //    orthogonal polar factor; |V^T V - I| ~ 1e-6 -> 1e-12 -> eps)
+    double *V0 = ws->w64, *V1 = ws->w64 + (size_t)n * n;   // n x n, ld n
+    k_to_f64<<<blocks_for((long)n * n), 256, 0, st>>>(ws->v32, n, V0, n, n, n);
+    HIP_TRY(hipGetLastError());
+    gemm1(true, false, n, n, n, V0, n, V0, n, ws->t64, n, st);
+    k_newton_schulz<<<blocks_for((long)n * n), 256, 0, st>>>(ws->t64, n);
+    gemm1(false, false, n, n, n, V0, n, ws->t64, n, V1, n, st);
+    gemm1(true, false, n, n, n, V1, n, V1, n, ws->t64, n, st);
+    k_newton_schulz<<<blocks_for((long)n * n), 256, 0, st>>>(ws->t64, n);
+    gemm1(false, false, n, n, n, V1, n, ws->t64, n, a.V, a.ldv, st);
+    HIP_TRY(hipGetLastError());
+    // 3. G <- G V0 in FP64 (the FP32 iterate is discarded)
+    gemm1(false, false, m, n, n, a.G, a.ldg, a.V, a.ldv, ws->w64, m, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpy2DAsync(a.G, sizeof(double) * a.ldg, ws->w64, sizeof(double) * m,
+                             sizeof(double) * m, n, hipMemcpyDeviceToDevice, st));
+    // 4. FP64 sweeps from G V0, accumulating onto V0
+    return block_sweeps<double>(ws, a, a.G, a.ldg, a.V, a.ldv, a.tol, a.max_sweeps, a.dctr, a.hctr,
+                                sweeps_done);
 }
 
 void block_workspace_free(BlockWorkspace *ws)
@@ -845,6 +1019,10 @@ void block_workspace_free(BlockWorkspace *ws)
     if (ws->partial) (void)hipFree(ws->partial);
     if (ws->vp) (void)hipFree(ws->vp);
     if (ws->flags) (void)hipFree(ws->flags);
+    if (ws->g32) (void)hipFree(ws->g32);
+    if (ws->v32) (void)hipFree(ws->v32);
+    if (ws->t64) (void)hipFree(ws->t64);
+    if (ws->w64) (void)hipFree(ws->w64);
     if (ws->tables) {
         BlockTables *t = (BlockTables *)ws->tables;
         if (t->d_outer) (void)hipFree(t->d_outer);

@@ -15,6 +15,7 @@ JEVD_OK, JEVD_EINVAL, JEVD_ENONFINITE, JEVD_ENOCONV, JEVD_EHIP, JEVD_ENOMEM = 0,
 ORD_ROWCYCLIC, ORD_MODULUS, ORD_MODMODULUS = 0, 1, 2
 VAR_POINTWISE, VAR_BLOCK_ORIENTED, VAR_FULL_BLOCK, VAR_AUTO = 0, 1, 2, 3
 PIVOT_NONE, PIVOT_SIGN = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
 INFO_MAX_SWEEPS = 64
 
 EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "jevd_validate",
@@ -27,14 +28,16 @@ K_PAIR_STEP, K_GRAM, K_PIVOT_SOLVE, K_UPDATE = 0, 1, 2, 3
 class jevd_opts(ctypes.Structure):
     _fields_ = [("ordering", ctypes.c_int), ("variant", ctypes.c_int), ("block", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("max_inner", ctypes.c_int),
-                ("accumulate_v", ctypes.c_int), ("pivot", ctypes.c_int)]
+                ("accumulate_v", ctypes.c_int), ("pivot", ctypes.c_int),
+                ("precision", ctypes.c_int)]
 
 
 class jevd_info(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int), ("variant", ctypes.c_int), ("block", ctypes.c_int),
                 ("ordering", ctypes.c_int), ("rotations", ctypes.c_longlong * INFO_MAX_SWEEPS),
                 ("clamps", ctypes.c_longlong), ("breakdowns", ctypes.c_longlong),
-                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_longlong * 4)]
+                ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_longlong * 4),
+                ("sweeps_low", ctypes.c_int)]
 
 
 class JevdError(RuntimeError):
@@ -269,7 +272,7 @@ class Solver:
 
     def evd(self, G, J=None, tol=0.0, ordering=ORD_MODMODULUS, variant=VAR_AUTO, block=0,
             max_sweeps=50, max_inner=30, want_U=True, want_V=True, V0=None, check=True,
-            pivot=PIVOT_NONE):
+            pivot=PIVOT_NONE, precision=PREC_FP64):
         """Solve in place on the device tensor G (float64, column-major: pass
         a tensor whose .T is contiguous, or any (m, n) tensor with stride
         (1, ldg)).  Returns (lam, U, V, sweeps, status)."""
@@ -288,6 +291,7 @@ class Solver:
         o.ordering, o.variant, o.block = ordering, variant, block
         o.max_sweeps, o.max_inner = max_sweeps, max_inner
         o.pivot = pivot
+        o.precision = precision
         if V0 is not None:
             V = V0
             o.accumulate_v = 1
