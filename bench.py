@@ -27,6 +27,13 @@ Workloads (seeded, synthetic; paper_1008_0201_amd/workloads.py):
   spd-graded-T-n8192-lam6: the same with lam = 10^U(-6,0) (the literal
       recipe; kappa(Q diag(lam) Q^T) = 1e6 limits FP64 relative accuracy to
       about 1e-10, so no method of this family meets a 1e-12 gate on it)
+  spd-graded-T-n4096-mixed: the block recipe above at n = 4096, mixed
+      precision (FP32-MFMA block sweeps, FP64 re-orthogonalisation of V0,
+      G V0, FP64 block sweeps); the FP64 block path on the same input is
+      timed beside it; work counts the FP32 and the FP64 sweeps
+  hyperbolic-graded-n4096-hfsc: G = B diag(10^U(-2,2)), 4096 x 4096, J =
+      diag(+1 x 2048, -1 x 2048), full block, b = 32, sign-pivoted Cholesky
+      (HFSC, Alg. 3.3); the unpivoted full block path (HF) is timed beside it
   batch-uneven-4096: 4096 independent instances, n_i ~ U{16..256}, m_i = n_i,
       even i positive definite (N(0,1)), odd i indefinite (columns graded
       10^U(-2,2), 30-70 % negative signs), modified modulus, tol_i = n_i eps;
@@ -67,6 +74,10 @@ def make_workload(name):
         return W.graded_spd_transposed(8192, lam_decades=3.0), dict(variant=1, block=32)
     if name == "spd-graded-T-n8192-lam6":
         return W.graded_spd_transposed(8192, lam_decades=6.0), dict(variant=1, block=32)
+    if name == "spd-graded-T-n4096-mixed":
+        return W.graded_spd_transposed(4096, lam_decades=3.0), dict(variant=1, block=32, precision=1)
+    if name == "hyperbolic-graded-n4096-hfsc":
+        return W.graded_hyperbolic(4096, k=6, grade=2.0), dict(variant=2, block=32, pivot=1)
     raise SystemExit("unknown workload %r" % name)
 
 
@@ -482,6 +493,8 @@ def main():
     opts.ordering = wl.ordering
     opts.variant = cfg["variant"]
     opts.block = cfg["block"]
+    opts.pivot = cfg.get("pivot", 0)
+    opts.precision = cfg.get("precision", 0)
 
     def step():
         Gd.copy_(G0)
@@ -512,6 +525,7 @@ def main():
     jevd.jevd_set_timing(h, False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     sweeps = sweeps_seen[-1]
+    sweeps_low = jevd.jevd_get_info(h).sweeps_low if opts.precision else 0
     block = cfg["variant"] != 0
     if block:
         b = cfg["block"]
@@ -520,8 +534,31 @@ def main():
     else:
         P = pairs_per_sweep(n, wl.ordering)
         work = P * (12.0 * m + 6.0 * n)
-    gflops = sweeps * work / (ms_per_step * 1e-3) / 1e9
+    gflops = (sweeps + sweeps_low) * work / (ms_per_step * 1e-3) / 1e9
     lam_gpu = np.sort(lam.cpu().numpy())
+
+    # the plain FP64 / unpivoted block path on the same input, beside the
+    # mixed-precision or sign-pivoted run
+    compare = None
+    if opts.precision or opts.pivot:
+        plain = jevd.jevd_default_opts()
+        plain.ordering, plain.variant, plain.block = opts.ordering, opts.variant, opts.block
+        lam_p = torch.empty_like(lam)
+        Gp = torch.empty_like(Gd)
+        t_p = []
+        for _ in range(2):
+            Gp.copy_(G0)
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            st_p, sw_p = jevd.jacobi_evd(h, m, n, Gp.data_ptr(), m, Jb, wl.tol, plain,
+                                         lam_p.data_ptr(), 0, m, 0, n)
+            torch.cuda.synchronize()
+            t_p.append((time.perf_counter() - tt) * 1e3)
+        lp = np.sort(lam_p.cpu().numpy())
+        compare = {"path": "FP64 block" if opts.precision else "unpivoted block (HF)",
+                   "status": st_p, "sweeps": sw_p, "ms_per_solve": round(min(t_p), 2),
+                   "speedup": round(min(t_p) / ms_per_step, 3),
+                   "max_rel_eig_diff": float(np.max(np.abs(lam_gpu - lp) / np.abs(lp)))}
 
     roofline = None
     kernels = None
@@ -579,7 +616,7 @@ def main():
             steps_sample = 1
             t = time.perf_counter()
             O.block_steps(wl.G, wl.J, wl.tol, b=b, full_block=cfg["variant"] == 2,
-                          steps=steps_sample)
+                          steps=steps_sample, sign_pivot=bool(opts.pivot))
             dt = time.perf_counter() - t
             w_sample = steps_sample * (N // 2) * (2.0 * b) ** 2 * 3.0 * m
             cpu = {"value": round(w_sample / dt / 1e9, 4), "unit": "GFLOP/s", "cores": 1,
@@ -602,17 +639,27 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded)",
-        "config": {"workload": wl.name, "m": m, "n": n,
+        "config": {"workload": args.workload if args.workload.startswith(wl.name) else wl.name,
+                   "m": m, "n": n,
                    "J": "I" if wl.J is None else "+%d/-%d" % (int((wl.J > 0).sum()), int((wl.J < 0).sum())),
                    "ordering": ["row-cyclic", "modulus", "modified modulus"][wl.ordering],
                    "variant": ["pointwise", "block-oriented", "full block"][cfg["variant"]],
                    "block": cfg["block"] if block else None,
                    "tol": wl.tol, "sweeps": sweeps, "want_U": True, "want_V": True,
+                   "pivot": ["none", "sign (Alg. 3.3)"][opts.pivot],
+                   "precision": ["fp64", "mixed (FP32 MFMA sweeps, then FP64)"][opts.precision],
                    "input_generation_s": round(t_gen, 1)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "accuracy": gate,
     }
+    if opts.precision:
+        out["config"]["sweeps_fp32"] = sweeps_low
+        if roofline:
+            roofline["note"] = ("k_update launches of both phases against the FP64 MFMA peak; "
+                                "the FP32 launches run on v_mfma_f32_16x16x4f32 (peak 157.3)")
+    if compare:
+        out["compare"] = compare
     if kernels:
         out["kernels"] = kernels
     jevd.jevd_destroy(h)

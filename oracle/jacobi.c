@@ -513,11 +513,11 @@ int SFX(orc_block_jevd_sp)(int m, int n, double *G, int ldg, const signed char *
  * of the block algorithm's work, used to time the oracle on inputs too large
  * to solve on the CPU.  Returns the status of the partial run. */
 int SFX(orc_block_steps)(int m, int n, double *G, int ldg, const signed char *J, double tol,
-                         int b, int full_block, int max_inner, int max_steps)
+                         int b, int full_block, int max_inner, int max_steps, int sign_pivot)
 {
     int sweeps = 0;
-    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, 0, 1, max_inner, 0, NULL, NULL,
-                           n, &sweeps, NULL, NULL, max_steps, NULL);
+    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, sign_pivot, 1, max_inner, 0, NULL,
+                           NULL, n, &sweeps, NULL, NULL, max_steps, NULL);
 }
 
 static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *J, double tol,

@@ -64,7 +64,7 @@ def lib():
             f.restype = ctypes.c_int
             f = getattr(L, "orc_block_steps_" + s)
             f.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _cp, ctypes.c_double,
-                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
             f.restype = ctypes.c_int
             f = getattr(L, "orc_rotation_" + s)
             f.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -187,7 +187,8 @@ def sp_cholesky(A, JP, prec="d"):
     return st, RS, perm, npos.value
 
 
-def block_steps(G, J=None, tol=None, b=32, full_block=False, max_inner=30, steps=1, prec="d"):
+def block_steps(G, J=None, tol=None, b=32, full_block=False, max_inner=30, steps=1, prec="d",
+                sign_pivot=False):
     """The first `steps` outer steps of one block sweep (a bounded sample of
     the block algorithm's work); returns (status, G after those steps)."""
     G, m, n, Jb, _ = _prep(G, J, False, None)
@@ -195,7 +196,7 @@ def block_steps(G, J=None, tol=None, b=32, full_block=False, max_inner=30, steps
         tol = n * np.finfo(np.float64).eps
     f = getattr(lib(), "orc_block_steps_" + prec)
     st = f(m, n, _ptr(G), m, None if Jb is None else Jb.ctypes.data_as(_cp), float(tol), b,
-           1 if full_block else 0, max_inner, steps)
+           1 if full_block else 0, max_inner, steps, 1 if sign_pivot else 0)
     return st, G
 
 

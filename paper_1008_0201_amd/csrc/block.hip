@@ -370,10 +370,11 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
             for (int l = j + tid; l < W; l += kPivotThreads)
                 VP[l * P + j] = (l == j) ? rjj : A[l * P + j] / rjj;
             __syncthreads();
-            const int nt = W - 1 - j;  // trailing order
-            for (int e = tid; e < nt * nt; e += kPivotThreads) {
-                const int i = j + 1 + e % nt, l = j + 1 + e / nt;
-                if (i <= l) A[l * P + i] -= VP[i * P + j] * VP[l * P + j];
+            // trailing update over a 16 x 16 thread grid (no integer
+            // division on the per-element path)
+            for (int l = j + 1 + (tid >> 4); l < W; l += kPivotThreads / 16) {
+                const double rl = VP[l * P + j];
+                for (int i = j + 1 + (tid & 15); i <= l; i += 16) A[l * P + i] -= VP[i * P + j] * rl;
             }
             __syncthreads();
         }
@@ -444,10 +445,11 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
             for (int l = j + tid; l < W; l += kPivotThreads)
                 VP[l * P + j] = (l == j) ? rjj : A[s_piv[l] * P + pj] / rjj;
             __syncthreads();
-            const int nt = W - 1 - j;
-            for (int e = tid; e < nt * nt; e += kPivotThreads) {
-                const int i = j + 1 + e % nt, l = j + 1 + e / nt;
-                A[s_piv[l] * P + s_piv[i]] -= VP[i * P + j] * VP[l * P + j];
+            for (int l = j + 1 + (tid >> 4); l < W; l += kPivotThreads / 16) {
+                const double rl = VP[l * P + j];
+                const int pl = s_piv[l];
+                for (int i = j + 1 + (tid & 15); i < W; i += 16)
+                    A[pl * P + s_piv[i]] -= VP[i * P + j] * rl;
             }
             __syncthreads();
         }
@@ -498,16 +500,23 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
             for (int s = 0; s < nsteps; ++s) {
                 int2 pq = make_int2(0, 1);
                 if (lane < NP) pq = inner_pair(a.all_pairs, W, s, lane);
-                const double *xp = A + pq.x * P + r0w, *xq = A + pq.y * P + r0w;
+                double *yp = A + pq.x * P + r0w, *yq = A + pq.y * P + r0w;
+                // this wavefront's rows of the pair stay in registers until
+                // the rotation (no other wavefront touches them in the step)
+                double xr[RPW], yr[RPW];
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    xr[r] = yp[r];
+                    yr[r] = yq[r];
+                }
                 // partial dot products over this wavefront's rows, added as a
                 // pairwise tree (rounding grows with log2(RPW), not RPW)
                 double sxx[RPW], syy[RPW], sxy[RPW];
 #pragma unroll
                 for (int r = 0; r < RPW; ++r) {
-                    const double x = xp[r], y = xq[r];
-                    sxx[r] = x * x;
-                    syy[r] = y * y;
-                    sxy[r] = x * y;
+                    sxx[r] = xr[r] * xr[r];
+                    syy[r] = yr[r] * yr[r];
+                    sxy[r] = xr[r] * yr[r];
                 }
 #pragma unroll
                 for (int h = RPW / 2; h > 0; h /= 2)
@@ -547,21 +556,26 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
                 double c = 1.0, sn = 0.0;
                 if (act && transform_params(app, aqq, apq, same, c, sn) && wave == 0) ++ncl;
                 if (act) {
-                    double *yp = A + pq.x * P + r0w, *yq = A + pq.y * P + r0w;
-#pragma unroll
-                    for (int r = 0; r < RPW; ++r) {
-                        double x = yp[r], y = yq[r];
-                        rotate_elems(x, y, c, sn, same);
-                        yp[r] = x;
-                        yq[r] = y;
-                    }
+                    // all loads first, then the arithmetic, then the stores:
+                    // one LDS latency instead of one per row
                     double *vp = VP + pq.x * P + r0w, *vq = VP + pq.y * P + r0w;
+                    double vx[RPW], vy[RPW];
 #pragma unroll
                     for (int r = 0; r < RPW; ++r) {
-                        double x = vp[r], y = vq[r];
-                        rotate_elems(x, y, c, sn, same);
-                        vp[r] = x;
-                        vq[r] = y;
+                        vx[r] = vp[r];
+                        vy[r] = vq[r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) {
+                        rotate_elems(xr[r], yr[r], c, sn, same);
+                        rotate_elems(vx[r], vy[r], c, sn, same);
+                    }
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) {
+                        yp[r] = xr[r];
+                        yq[r] = yr[r];
+                        vp[r] = vx[r];
+                        vq[r] = vy[r];
                     }
                     if (wave == 0) ++rot_it;
                 }
