@@ -50,7 +50,16 @@ struct InstCtx {
     double *sums;          // LDS: 3 per pair of a step (app, aqq, apq)
     double *rotcs;         // LDS: 2 per pair (c, s)
     int *flag;             // LDS: per pair: 0 none, 1 trigonometric, 2 hyperbolic
+    // deferred V (G in HBM): the transforms of up to vsteps steps are logged
+    // in LDS and applied to V in row blocks, so V is read and written once
+    // per vsteps steps instead of once per step
+    int vsteps;            // 0: V is rotated at once
+    double *vlog;          // LDS: vsteps x (n/2 + 1) x (c, s)
+    int *vflag;            // LDS: vsteps x (n/2 + 1) transform types
+    double *vrows;         // LDS: kBatchWaves * kVRows rows of V, n each
 };
+
+constexpr int kVRows = 2;   // rows of V per wavefront in the deferred apply
 
 // LDS bytes kept beside G and V: the signs and the per-pair step arrays.
 // Rounded to 16 bytes so that the arrays at the top of LDS stay aligned.
@@ -181,9 +190,15 @@ __device__ __forceinline__ void modulus_step(double *g, long ldg, double *v, lon
 template <int R>
 __device__ __forceinline__ void two_pairs(double *g, long ldg, double *v, long ldv,
                                           const InstCtx &c, int p0, int q0, bool has1, int p1,
-                                          int q1, int lane, unsigned &rot, int &bad)
+                                          int q1, int lane, unsigned &rot, int &bad,
+                                          double *logcs = nullptr, int *logfl = nullptr,
+                                          int e0 = 0, int e1 = 0)
 {
-    const int pp[2] = {p0, p1}, qq[2] = {q0, q1};
+    const int pp[2] = {p0, p1}, qq[2] = {q0, q1}, ee[2] = {e0, e1};
+    if (logfl && lane == 0) {   // every logged pair gets an entry; rotated ones overwrite it
+        logfl[e0] = 0;
+        if (has1) logfl[e1] = 0;
+    }
     double a[2][R], b[2][R], va[2][R], vb[2][R];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -230,6 +245,11 @@ __device__ __forceinline__ void two_pairs(double *g, long ldg, double *v, long l
         const bool same = c.J[pp[k]] == c.J[qq[k]];
         double cs, sn;
         transform_params(app[k], aqq[k], apq[k], same, cs, sn);
+        if (logfl && lane == 0) {
+            logcs[2 * ee[k]] = cs;
+            logcs[2 * ee[k] + 1] = sn;
+            logfl[ee[k]] = same ? 1 : 2;
+        }
         double *gp = g + (size_t)pp[k] * ldg, *gq = g + (size_t)qq[k] * ldg;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
@@ -261,7 +281,7 @@ __device__ __forceinline__ void two_pairs(double *g, long ldg, double *v, long l
 template <int R>
 __device__ __forceinline__ void global_step(double *g, long ldg, double *v, long ldv,
                                             const InstCtx &c, int k, bool modified, unsigned &rot,
-                                            int &bad)
+                                            int &bad, double *logcs, int *logfl)
 {
     constexpr int NW = kBatchWaves;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -272,16 +292,69 @@ __device__ __forceinline__ void global_step(double *g, long ldg, double *v, long
             modulus_pair(c.n, k, e, &p0, &q0);
             const bool has1 = e + NW < np;
             if (has1) modulus_pair(c.n, k, e + NW, &p1, &q1);
-            two_pairs<R>(g, ldg, v, ldv, c, p0, q0, has1, p1, q1, lane, rot, bad);
+            two_pairs<R>(g, ldg, v, ldv, c, p0, q0, has1, p1, q1, lane, rot, bad, logcs, logfl, e,
+                         e + NW);
         }
     } else {
         for (int e = wave; e < np; e += NW) {
             int p, q;
             modulus_pair(c.n, k, e, &p, &q);
-            two_pairs<R>(g, ldg, v, ldv, c, p, q, false, 0, 0, lane, rot, bad);
+            two_pairs<R>(g, ldg, v, ldv, c, p, q, false, 0, 0, lane, rot, bad, logcs, logfl, e, 0);
         }
     }
     __syncthreads();
+}
+
+// Applies the logged transforms of steps kfirst .. kfirst + nsteps - 1 to V
+// (HBM, column-major): blocks of kBatchWaves * kVRows rows are staged in LDS;
+// a wavefront owns kVRows rows and runs every logged step on them, lanes over
+// the step's pairs.  A row's elements are rotated in the same order as by
+// immediate application, so V is the same to the bit.
+__device__ __forceinline__ void apply_v_log(double *v, long ldv, const InstCtx &c, int kfirst,
+                                            int nsteps, bool modified)
+{
+    constexpr int NW = kBatchWaves, BS = NW * 64, RB = NW * kVRows;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = c.n, lp = n / 2 + 1;
+    for (int r0 = 0; r0 < n; r0 += RB) {
+        const int nr = min(RB, n - r0);
+        for (int e = tid; e < RB * n; e += BS) {
+            const int i = e % RB, col = e / RB;
+            if (i < nr) c.vrows[i * n + col] = v[(size_t)col * ldv + r0 + i];
+        }
+        __syncthreads();
+        for (int ii = 0; ii < kVRows; ++ii) {
+            const int i = wave * kVRows + ii;
+            if (i >= nr) break;
+            double *row = c.vrows + (size_t)i * n;
+            for (int st = 0; st < nsteps; ++st) {
+                const int k = kfirst + st;
+                const int np = modulus_step_pairs(n, k, modified);
+                for (int e = lane; e < np; e += 64) {
+                    const int f = c.vflag[st * lp + e];
+                    if (f == 0) continue;
+                    int p, q;
+                    modulus_pair(n, k, e, &p, &q);
+                    double x = row[p], y = row[q];
+                    rotate_elems(x, y, c.vlog[2 * (st * lp + e)], c.vlog[2 * (st * lp + e) + 1], f == 1);
+                    row[p] = x;
+                    row[q] = y;
+                }
+                // the next step's pairs read columns other lanes wrote: the
+                // LDS accesses of one wavefront complete in order, and the
+                // fences keep the compiler from moving them across
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < RB * n; e += BS) {
+            const int i = e % RB, col = e / RB;
+            if (i < nr) v[(size_t)col * ldv + r0 + i] = c.vrows[i * n + col];
+        }
+        __syncthreads();
+    }
 }
 
 // One pair with rows looped over by one wavefront (the row-cyclic path).
@@ -346,9 +419,23 @@ __device__ __forceinline__ int sweep_instance(double *g, long ldg, double *v, lo
                 for (int p = 0; p < n - 1; ++p)
                     for (int q = p + 1; q < n; ++q) one_pair_loop(g, ldg, v, ldv, c, p, q, lane, rot, bad);
         } else {
-            for (int k = 1; k <= n; ++k) {
-                if constexpr (R > 0) global_step<R>(g, ldg, v, ldv, c, k, ordering == kOrdModModulus, rot, bad);
-                else modulus_step(g, ldg, v, ldv, c, k, ordering == kOrdModModulus, rot, bad);
+            const bool modified = ordering == kOrdModModulus;
+            if constexpr (R > 0) {
+                const bool defer = v && c.vsteps > 0;
+                const int lp = n / 2 + 1;
+                int inchunk = 0, kfirst = 1;
+                for (int k = 1; k <= n; ++k) {
+                    global_step<R>(g, ldg, defer ? nullptr : v, ldv, c, k, modified, rot, bad,
+                                   defer ? c.vlog + 2 * (size_t)inchunk * lp : nullptr,
+                                   defer ? c.vflag + (size_t)inchunk * lp : nullptr);
+                    if (defer && (++inchunk == c.vsteps || k == n)) {
+                        apply_v_log(v, ldv, c, kfirst, inchunk, modified);
+                        inchunk = 0;
+                        kfirst = k + 1;
+                    }
+                }
+            } else {
+                for (int k = 1; k <= n; ++k) modulus_step(g, ldg, v, ldv, c, k, modified, rot, bad);
             }
         }
         // workgroup totals: rotations and the non-finite flag
@@ -424,6 +511,24 @@ __global__ __launch_bounds__(kBatchWaves * 64) void k_batch_solve(
         c.flag = (int *)(c.rotcs + 2 * pairs);
         signed char *sJ = (signed char *)(c.flag + pairs);
         c.J = sJ;
+        c.vsteps = 0;
+        c.vlog = nullptr;
+        c.vflag = nullptr;
+        c.vrows = nullptr;
+        if (!lg && d.V && m <= 256) {
+            // G in HBM (the register path): LDS below the step arrays holds
+            // the V row blocks and the transform log of vsteps steps
+            const size_t free_bytes = kBatchLdsBytes - aux;
+            const size_t rows_bytes = (size_t)kBatchWaves * kVRows * n * sizeof(double);
+            const size_t per_step = pairs * (2 * sizeof(double) + sizeof(int));
+            if (free_bytes > rows_bytes + 4 * per_step) {
+                size_t vs = (free_bytes - rows_bytes) / per_step;
+                c.vsteps = (int)(vs > 32 ? 32 : vs);
+                c.vrows = lds;
+                c.vlog = lds + (size_t)kBatchWaves * kVRows * n;
+                c.vflag = (int *)(c.vlog + 2 * (size_t)c.vsteps * pairs);
+            }
+        }
         for (int e = tid; e < n; e += BS) sJ[e] = (d.J && d.J[e] < 0) ? -1 : 1;
         if (lg)
             for (int e = tid; e < m * n; e += BS) lds[e] = d.G[(size_t)(e / m) * d.ldg + (e % m)];

@@ -405,22 +405,20 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
         for (int j = 0; j < W; ++j) {
             const int hi = (j < npos) ? npos : W;
             if (wave == 0) {
+                // the largest remaining diagonal entry: DPP max within rows of
+                // 16 lanes, then across the four rows; the first lane holding
+                // it gives the position (the entries are finite here)
                 const int i = j + lane;
-                double v = -1.0;
-                int idx = W;
-                if (i < hi) {
-                    v = A[s_piv[i] * P + s_piv[i]];
-                    idx = i;
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double ov = __shfl_xor(v, off);
-                    const int oi = __shfl_xor(idx, off);
-                    if (ov > v || (ov == v && oi < idx)) {
-                        v = ov;
-                        idx = oi;
-                    }
-                }
-                const int t = idx;   // the same in every lane
+                const double v = (i < hi) ? A[s_piv[i] * P + s_piv[i]] : -1.0;
+                double mx = v;
+                mx = fmax(mx, dpp_move<0xB1>(mx));
+                mx = fmax(mx, dpp_move<0x4E>(mx));
+                mx = fmax(mx, dpp_move<0x141>(mx));
+                mx = fmax(mx, dpp_move<0x140>(mx));
+                mx = fmax(fmax(read_lane(mx, 0), read_lane(mx, 16)),
+                          fmax(read_lane(mx, 32), read_lane(mx, 48)));
+                const unsigned long long hit = __ballot(i < hi && v == mx);
+                const int t = hit ? j + __ffsll((long long)hit) - 1 : W;   // the same in every lane
                 if (t != j && t < W) {
                     if (lane < j) {
                         const double x = VP[j * P + lane];
