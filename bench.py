@@ -203,13 +203,29 @@ def run_batched(args):
                for s, m, n in zip(sw, ms, ns))
     gflops = work / (ms_per_step * 1e-3) / 1e9
     achieved = work / (kern_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": 78.6,
-                "unit": "TFLOP/s", "frac": round(achieved / 78.6, 4), "traffic": None,
-                "kernel": "k_batch_solve", "avg_launch_us": round(kern_ms * 1e3, 1),
-                "flops_per_launch": work,
+    # HBM bytes of the instances too large for LDS (G and V of an instance
+    # stay on chip when m n 8 (+ n^2 8) and the step arrays fit 160 KiB):
+    # each parallel step reads and writes G (16 m n bytes); V is read and
+    # written once per 32 logged steps; every instance loads and stores G, V
+    # once.  These streams dominate the launch.
+    lds = 160 * 1024 - 256
+    hbm = 0.0
+    for s_i, m_i, n_i in zip(sw, ms, ns):
+        pairs = n_i // 2 + 1
+        aux = (pairs * 44 + n_i + 15) // 16 * 16
+        hbm += 16.0 * (m_i * n_i + n_i * n_i)   # load and store G, V
+        if m_i * n_i * 8 + aux > lds:
+            hbm += s_i * n_i * (16.0 * m_i * n_i + 16.0 * n_i * n_i / 32.0)
+    bw = hbm / (kern_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(bw / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_batch_solve",
+                "avg_launch_us": round(kern_ms * 1e3, 1), "bytes_per_launch": hbm,
+                "flops_per_launch": work, "fp64_vector_tflops": round(achieved, 3),
                 "timing": "HIP events around jevd_batch_run (queue reset + one persistent "
                           "launch) on the solver stream",
-                "peak_basis": "FP64 vector FMA: 256 CUs x 64 lanes x 2 flops x 2.4 GHz"}
+                "bytes_basis": "instances with G in HBM: 16 m n bytes per parallel step (G read "
+                               "and written) + V once per 32 steps; all: G, V loaded and stored "
+                               "once"}
 
     # the same instances one jacobi_evd call at a time (a sample)
     nloop = 256

@@ -117,3 +117,38 @@ def test_batch_entry_points_reject_null_arguments():
     assert L.jevd_batch_destroy(None) == B.JEVD_OK
     assert L.jacobi_evd_batched(None, 1, m, m, None, m, None, None, None, None, None, None, None,
                                 None, None, None) == B.JEVD_EINVAL
+
+
+def test_adjoint_entry_points_reject_bad_arguments():
+    """jevd_canonicalize and jevd_adjoint check sizes and pointers on the
+    host before any device work."""
+    L = B.lib()
+    vp = ctypes.c_void_p
+    # null handle
+    assert L.jevd_canonicalize(None, 1, 4, 4, vp(8), 4, vp(8), 4, 16, None, 4, 16, vp(8), vp(8),
+                               None) == B.JEVD_EINVAL
+    assert L.jevd_adjoint(None, 1, 4, 4, vp(8), 4, 16, None, 4, vp(8), 4, vp(8), 4, 16, None, 4,
+                          None, 4, 16, vp(8), 4, 16) == B.JEVD_EINVAL
+    assert B.jevd_strerror(B.JEVD_EINVAL)
+
+
+def test_opts_struct_matches_header():
+    """The binding's jevd_opts / jevd_info layouts follow include/jevd.h."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "jevd.h")).read()
+    opts = hdr[hdr.index("typedef struct {"):hdr.index("} jevd_opts;")]
+    fields = re.findall(r"^\s+int (\w+);", opts, re.M)
+    assert fields == [f for f, _ in B.jevd_opts._fields_]
+    o = B.jevd_default_opts()
+    assert (o.ordering, o.variant, o.block, o.max_sweeps, o.max_inner, o.accumulate_v, o.pivot,
+            o.precision) == (B.ORD_MODMODULUS, B.VAR_AUTO, 0, 50, 30, 0, B.PIVOT_NONE, B.PREC_FP64)
+    for bad in (dict(pivot=2), dict(precision=2), dict(pivot=1, variant=0), dict(precision=1, variant=0)):
+        o = B.jevd_default_opts()
+        for k, v in bad.items():
+            setattr(o, k, v)
+        assert B.jevd_validate(64, 64, 64, None, 0.0, o, False, 64, False, 64) == B.JEVD_EINVAL, bad
+    o = B.jevd_default_opts()
+    o.variant, o.block, o.precision = 1, 16, 1
+    J = bytes([1] * 63 + [255])
+    assert B.jevd_validate(64, 64, 64, J, 0.0, o, False, 64, False, 64) == B.JEVD_EINVAL
+    assert B.jevd_validate(64, 64, 64, None, 0.0, o, False, 64, False, 64) == B.JEVD_OK
