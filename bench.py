@@ -31,6 +31,7 @@ Workloads (seeded, synthetic; paper_1008_0201_amd/workloads.py):
       precision (FP32-MFMA block sweeps, FP64 re-orthogonalisation of V0,
       G V0, FP64 block sweeps); the FP64 block path on the same input is
       timed beside it; work counts the FP32 and the FP64 sweeps
+  spd-graded-T-n8192-mixed: the same at n = 8192
   hyperbolic-graded-n4096-hfsc: G = B diag(10^U(-2,2)), 4096 x 4096, J =
       diag(+1 x 2048, -1 x 2048), full block, b = 32, sign-pivoted Cholesky
       (HFSC, Alg. 3.3); the unpivoted full block path (HF) is timed beside it
@@ -76,6 +77,8 @@ def make_workload(name):
         return W.graded_spd_transposed(8192, lam_decades=6.0), dict(variant=1, block=32)
     if name == "spd-graded-T-n4096-mixed":
         return W.graded_spd_transposed(4096, lam_decades=3.0), dict(variant=1, block=32, precision=1)
+    if name == "spd-graded-T-n8192-mixed":
+        return W.graded_spd_transposed(8192, lam_decades=3.0), dict(variant=1, block=32, precision=1)
     if name == "hyperbolic-graded-n4096-hfsc":
         return W.graded_hyperbolic(4096, k=6, grade=2.0), dict(variant=2, block=32, pivot=1)
     raise SystemExit("unknown workload %r" % name)
@@ -487,6 +490,8 @@ def main():
     ap.add_argument("--workload", default="hyperbolic-graded-n1024")
     ap.add_argument("--variant", type=int, default=None, help="override: 0 pointwise, 1 BO, 2 FB")
     ap.add_argument("--block", type=int, default=None)
+    ap.add_argument("--precision", type=int, default=None, help="override: 0 FP64, 1 mixed")
+    ap.add_argument("--pivot", type=int, default=None, help="override: 0 none, 1 sign (Alg. 3.3)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (profiling runs); no accuracy gate then")
     args = ap.parse_args()
@@ -512,6 +517,10 @@ def main():
         cfg["variant"] = args.variant
     if args.block is not None:
         cfg["block"] = args.block
+    if args.precision is not None:
+        cfg["precision"] = args.precision
+    if args.pivot is not None:
+        cfg["pivot"] = args.pivot
     m, n = wl.m, wl.n
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
@@ -584,11 +593,12 @@ def main():
             torch.cuda.synchronize()
             tt = time.perf_counter()
             st_p, sw_p = jevd.jacobi_evd(h, m, n, Gp.data_ptr(), m, Jb, wl.tol, plain,
-                                         lam_p.data_ptr(), 0, m, 0, n)
+                                         lam_p.data_ptr(), U.data_ptr(), m, V.data_ptr(), n)
             torch.cuda.synchronize()
             t_p.append((time.perf_counter() - tt) * 1e3)
         lp = np.sort(lam_p.cpu().numpy())
-        compare = {"path": "FP64 block" if opts.precision else "unpivoted block (HF)",
+        compare = {"path": ("FP64 block" if opts.precision else "unpivoted block (HF)") +
+                           ", U and V formed as in the timed run",
                    "status": st_p, "sweeps": sw_p, "ms_per_solve": round(min(t_p), 2),
                    "speedup": round(min(t_p) / ms_per_step, 3),
                    "max_rel_eig_diff": float(np.max(np.abs(lam_gpu - lp) / np.abs(lp)))}
