@@ -194,6 +194,158 @@ __global__ __launch_bounds__(256) void k_sum_slots(unsigned *__restrict__ slot_r
     }
 }
 
+// One pair of a step by one wavefront, lanes over the rows.  When the rows
+// fit R per lane (m, n <= 64 R) they stay in registers from the dot products
+// to the rotation and the V pair is loaded with the G pair; otherwise the
+// rows are looped over (R = 0).
+template <int R>
+__device__ __forceinline__ void small_pair(double *g, long lg, double *v, long lv, int m, int n,
+                                           int p, int q, const signed char *J, double tol,
+                                           int lane, unsigned long long &rot,
+                                           unsigned long long &ncl, int *nonfinite)
+{
+    double *gp = g + (size_t)p * lg, *gq = g + (size_t)q * lg;
+    if constexpr (R > 0) {
+        double a[R], b[R], va[R], vb[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = lane + kWave * i;
+            a[i] = r < m ? gp[r] : 0.0;
+            b[i] = r < m ? gq[r] : 0.0;
+        }
+        if (v) {
+            const double *vp = v + (size_t)p * lv, *vq = v + (size_t)q * lv;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = lane + kWave * i;
+                va[i] = r < n ? vp[r] : 0.0;
+                vb[i] = r < n ? vq[r] : 0.0;
+            }
+        }
+        double app = 0.0, aqq = 0.0, apq = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            app = fma(a[i], a[i], app);
+            aqq = fma(b[i], b[i], aqq);
+            apq = fma(a[i], b[i], apq);
+        }
+        app = wave_sum(app);
+        aqq = wave_sum(aqq);
+        apq = wave_sum(apq);
+        if (!finite3(app, aqq, apq)) {
+            *nonfinite = 1;
+            return;
+        }
+        if (!needs_rotation(app, aqq, apq, tol)) return;
+        const bool same = (J == nullptr) || (J[p] == J[q]);
+        double c, s;
+        ncl += transform_params(app, aqq, apq, same, c, s) ? 1 : 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = lane + kWave * i;
+            rotate_elems(a[i], b[i], c, s, same);
+            if (r < m) {
+                gp[r] = a[i];
+                gq[r] = b[i];
+            }
+        }
+        if (v) {
+            double *vp = v + (size_t)p * lv, *vq = v + (size_t)q * lv;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int r = lane + kWave * i;
+                rotate_elems(va[i], vb[i], c, s, same);
+                if (r < n) {
+                    vp[r] = va[i];
+                    vq[r] = vb[i];
+                }
+            }
+        }
+        ++rot;
+    } else {
+        double app = 0.0, aqq = 0.0, apq = 0.0;
+        for (int r = lane; r < m; r += kWave) {
+            const double a = gp[r], b = gq[r];
+            app = fma(a, a, app);
+            aqq = fma(b, b, aqq);
+            apq = fma(a, b, apq);
+        }
+        app = wave_sum(app);
+        aqq = wave_sum(aqq);
+        apq = wave_sum(apq);
+        if (!finite3(app, aqq, apq)) {
+            *nonfinite = 1;
+            return;
+        }
+        if (!needs_rotation(app, aqq, apq, tol)) return;
+        const bool same = (J == nullptr) || (J[p] == J[q]);
+        double c, s;
+        ncl += transform_params(app, aqq, apq, same, c, s) ? 1 : 0;
+        for (int r = lane; r < m; r += kWave) {
+            double a = gp[r], b = gq[r];
+            rotate_elems(a, b, c, s, same);
+            gp[r] = a;
+            gq[r] = b;
+        }
+        if (v) {
+            double *vp = v + (size_t)p * lv, *vq = v + (size_t)q * lv;
+            for (int r = lane; r < n; r += kWave) {
+                double a = vp[r], b = vq[r];
+                rotate_elems(a, b, c, s, same);
+                vp[r] = a;
+                vq[r] = b;
+            }
+        }
+        ++rot;
+    }
+}
+
+// All sweeps on (g, v).  The caller passes pointers of one kind (LDS or
+// global) for g and for v, so that the accesses compile to LDS or global
+// instructions rather than generic ones.
+template <int NW, int R>
+__device__ __forceinline__ int small_sweeps(double *g, long lg, double *v, long lv, int m, int n,
+                                            const signed char *J, double tol, const int2 *pairs,
+                                            const int *step_start, int nsteps, int max_sweeps,
+                                            SweepCounters *ctr, unsigned long long *red,
+                                            int *nonfinite)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    int sweep = 0;
+    while (sweep < max_sweeps) {
+        unsigned long long rot = 0, ncl = 0;
+        for (int st = 0; st < nsteps; ++st) {
+            const int e0 = step_start[st], e1 = step_start[st + 1];
+            for (int e = e0 + wave; e < e1; e += NW) {
+                const int2 pq = pairs[e];
+                small_pair<R>(g, lg, v, lv, m, n, pq.x, pq.y, J, tol, lane, rot, ncl, nonfinite);
+            }
+            if constexpr (NW > 1) __syncthreads();
+        }
+        if (lane == 0) {
+            red[wave] = rot;
+            red[NW + wave] = ncl;
+        }
+        __syncthreads();
+        unsigned long long tot = 0, totc = 0;
+        for (int i = 0; i < NW; ++i) {
+            tot += red[i];
+            totc += red[NW + i];
+        }
+        const int nf = *nonfinite;
+        if (threadIdx.x == 0) {
+            ctr[sweep].rotations = tot;
+            ctr[sweep].clamps = totc;
+            ctr[sweep].nonfinite = nf;
+        }
+        ++sweep;
+        __syncthreads();
+        if (tot == 0 || nf) break;
+    }
+    return sweep;
+}
+
 // Whole solve in one workgroup of NW wavefronts.  The pairs of each step
 // are dealt round-robin to the wavefronts; lanes of a wavefront run over the
 // rows.  If `lds_g` the m x n factor lives in LDS (leading dimension m), and
@@ -209,102 +361,41 @@ __global__ __launch_bounds__(NW *kWave) void k_small_solve(
     extern __shared__ double lds[];
     __shared__ unsigned long long red[2 * NW];
     __shared__ int nonfinite;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
     constexpr int BS = NW * kWave;
 
-    double *g = G;
-    long lg = ldg;
-    double *v = V;
-    long lv = ldv;
-    if (lds_g) {
-        g = lds;
-        lg = m;
+    if (lds_g)
         for (int c = 0; c < n; ++c)
-            for (int r = threadIdx.x; r < m; r += BS) g[r + (size_t)c * m] = G[r + (size_t)c * ldg];
-    }
-    if (V && lds_v) {
-        v = lds + (lds_g ? (size_t)m * n : 0);
-        lv = n;
+            for (int r = threadIdx.x; r < m; r += BS) lds[r + (size_t)c * m] = G[r + (size_t)c * ldg];
+    if (V && lds_v)
         for (int c = 0; c < n; ++c)
-            for (int r = threadIdx.x; r < n; r += BS) v[r + (size_t)c * n] = V[r + (size_t)c * ldv];
-    }
+            for (int r = threadIdx.x; r < n; r += BS)
+                lds[(size_t)m * n + r + (size_t)c * n] = V[r + (size_t)c * ldv];
     if (threadIdx.x == 0) nonfinite = 0;
     __syncthreads();
 
-    int sweep = 0;
-    while (sweep < max_sweeps) {
-        unsigned long long rot = 0, ncl = 0;
-        for (int st = 0; st < nsteps; ++st) {
-            const int e0 = step_start[st], e1 = step_start[st + 1];
-            for (int e = e0 + wave; e < e1; e += NW) {
-                const int2 pq = pairs[e];
-                double *gp = g + (size_t)pq.x * lg;
-                double *gq = g + (size_t)pq.y * lg;
-                double app = 0.0, aqq = 0.0, apq = 0.0;
-                for (int r = lane; r < m; r += kWave) {
-                    const double a = gp[r], b = gq[r];
-                    app = fma(a, a, app);
-                    aqq = fma(b, b, aqq);
-                    apq = fma(a, b, apq);
-                }
-                app = wave_sum(app);
-                aqq = wave_sum(aqq);
-                apq = wave_sum(apq);
-                if (!finite3(app, aqq, apq)) {
-                    nonfinite = 1;
-                    continue;
-                }
-                if (!needs_rotation(app, aqq, apq, tol)) continue;
-                const bool same = (J == nullptr) || (J[pq.x] == J[pq.y]);
-                double c, s;
-                ncl += transform_params(app, aqq, apq, same, c, s) ? 1 : 0;
-                for (int r = lane; r < m; r += kWave) {
-                    double a = gp[r], b = gq[r];
-                    rotate_elems(a, b, c, s, same);
-                    gp[r] = a;
-                    gq[r] = b;
-                }
-                if (V) {
-                    double *vp = v + (size_t)pq.x * lv;
-                    double *vq = v + (size_t)pq.y * lv;
-                    for (int r = lane; r < n; r += kWave) {
-                        double a = vp[r], b = vq[r];
-                        rotate_elems(a, b, c, s, same);
-                        vp[r] = a;
-                        vq[r] = b;
-                    }
-                }
-                ++rot;
-            }
-            if constexpr (NW > 1) __syncthreads();
-        }
-        if (lane == 0) {
-            red[wave] = rot;
-            red[NW + wave] = ncl;
-        }
-        __syncthreads();
-        unsigned long long tot = 0, totc = 0;
-        for (int i = 0; i < NW; ++i) {
-            tot += red[i];
-            totc += red[NW + i];
-        }
-        const int nf = nonfinite;
-        if (threadIdx.x == 0) {
-            ctr[sweep].rotations = tot;
-            ctr[sweep].clamps = totc;
-            ctr[sweep].nonfinite = nf;
-        }
-        ++sweep;
-        __syncthreads();
-        if (tot == 0 || nf) break;
+    const bool regs = m <= 2 * kWave && n <= 2 * kWave;
+    int sweep;
+    if (lds_g && V && lds_v) {
+        sweep = regs ? small_sweeps<NW, 2>(lds, m, lds + (size_t)m * n, n, m, n, J, tol, pairs,
+                                           step_start, nsteps, max_sweeps, ctr, red, &nonfinite)
+                     : small_sweeps<NW, 0>(lds, m, lds + (size_t)m * n, n, m, n, J, tol, pairs,
+                                           step_start, nsteps, max_sweeps, ctr, red, &nonfinite);
+    } else if (lds_g) {
+        sweep = regs ? small_sweeps<NW, 2>(lds, m, V, ldv, m, n, J, tol, pairs, step_start, nsteps,
+                                           max_sweeps, ctr, red, &nonfinite)
+                     : small_sweeps<NW, 0>(lds, m, V, ldv, m, n, J, tol, pairs, step_start, nsteps,
+                                           max_sweeps, ctr, red, &nonfinite);
+    } else {
+        sweep = small_sweeps<NW, 0>(G, ldg, V, ldv, m, n, J, tol, pairs, step_start, nsteps,
+                                    max_sweeps, ctr, red, &nonfinite);
     }
     if (lds_g)
         for (int c = 0; c < n; ++c)
-            for (int r = threadIdx.x; r < m; r += BS) G[r + (size_t)c * ldg] = g[r + (size_t)c * m];
+            for (int r = threadIdx.x; r < m; r += BS) G[r + (size_t)c * ldg] = lds[r + (size_t)c * m];
     if (V && lds_v)
         for (int c = 0; c < n; ++c)
-            for (int r = threadIdx.x; r < n; r += BS) V[r + (size_t)c * ldv] = v[r + (size_t)c * n];
+            for (int r = threadIdx.x; r < n; r += BS)
+                V[r + (size_t)c * ldv] = lds[(size_t)m * n + r + (size_t)c * n];
     if (threadIdx.x == 0) *sweeps_out = sweep;
 }
 
