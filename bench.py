@@ -84,13 +84,15 @@ def make_workload(name):
     raise SystemExit("unknown workload %r" % name)
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
-    summary (profiles/traffic.json), or None if absent or if the kernel's
-    sources changed since the counters were taken."""
+    summary (profiles/traffic.json), or None if absent, if it was taken on
+    another workload, or if the kernel's sources changed since."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        if workload is not None and rec.get("workload") != workload:
+            return None
         h = hashlib.sha256()
         for f in rec["sources"]:
             h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -221,7 +223,9 @@ def run_batched(args):
             hbm += s_i * n_i * (16.0 * m_i * n_i + 16.0 * n_i * n_i / 32.0)
     bw = hbm / (kern_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(bw, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(bw / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_batch_solve",
+                "frac": round(bw / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("k_batch_solve", "batch-uneven-4096"),
+                "kernel": "k_batch_solve",
                 "avg_launch_us": round(kern_ms * 1e3, 1), "bytes_per_launch": hbm,
                 "flops_per_launch": work, "fp64_vector_tflops": round(achieved, 3),
                 "timing": "HIP events around jevd_batch_run (queue reset + one persistent "
@@ -613,7 +617,7 @@ def main():
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic("k_pair_step") if wl.name == "hyperbolic-graded-n1024" else None,
+                    "traffic": measured_traffic("k_pair_step", wl.name),
                     "kernel": "k_pair_step", "avg_launch_us": round(avg_ms * 1e3, 3),
                     "bytes_per_launch": bytes_per_launch,
                     "timing": "HIP events around each sweep's launches on the solver stream; "
@@ -626,7 +630,9 @@ def main():
         achieved = flops_update / (avg_ms * 1e-3) / 1e12
         roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_MFMA_PEAK_TFS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFS, 4),
-                    "traffic": None, "kernel": "k_update",
+                    "traffic": (measured_traffic("k_update", args.workload)
+                                if not (opts.precision or opts.pivot) else None),
+                    "kernel": "k_update",
                     "avg_launch_us": round(avg_ms * 1e3, 3), "flops_per_launch": flops_update}
         flops_gram = npiv * (2.0 * b) ** 2 * m
         kernels = {name: {"ms_per_solve": round(kms[c] / args.steps, 3),
