@@ -688,7 +688,11 @@ __global__ __launch_bounds__(256) void k_update(T *__restrict__ G, int m, long l
         typename Mfma<T>::acc acc[NT];
 #pragma unroll
         for (int q = 0; q < NT; ++q) acc[q] = typename Mfma<T>::acc{0, 0, 0, 0};
-#pragma unroll
+        // partly unrolled: fully unrolled, the V_P fragments of all k-steps
+        // are hoisted into registers (198 VGPRs, two wavefronts per SIMD);
+        // two passes of eight k-steps keep three resident and measured
+        // 10 % faster at n = 8192
+#pragma unroll 8
         for (int ks = 0; ks < KS; ++ks) {
             const T *srow = S + (4 * ks + lane / 16) * SP + (lane % 16);
 #pragma unroll
