@@ -67,13 +67,77 @@ __device__ __forceinline__ int pivot_col(int k, int2 IJ, int b)
 }
 
 // ------------------------------------------------------------------ k_gram
+// Tile t of the upper triangle of NT x NT tiles, row-major: row and column.
+__host__ __device__ constexpr int upper_tile_i(int NT, int t)
+{
+    int it = 0;
+    while (t >= NT - it) {   // row it of the upper triangle has NT - it tiles
+        t -= NT - it;
+        ++it;
+    }
+    return it;
+}
+__host__ __device__ constexpr int upper_tile_j(int NT, int t)
+{
+    int it = 0;
+    while (t >= NT - it) {
+        t -= NT - it;
+        ++it;
+    }
+    return it + t;
+}
+
+// The MFMAs of one staged slab for wavefront WV: tiles WV, WV + 4, ... of
+// the upper triangle (past the last tile, tile 0 again), all indices known at
+// compile time.  Each k-step reads the NT column-block operands once; the
+// reads of step k + 1 are issued before the MFMAs of step k.
+template <int NT, int WV, int Q>
+struct GramTile {
+    static constexpr int t = (WV + 4 * Q < NT * (NT + 1) / 2) ? WV + 4 * Q : 0;
+    static constexpr int i = upper_tile_i(NT, t);
+    static constexpr int j = upper_tile_j(NT, t);
+};
+
+template <int W, class T, int KR, int LDC, int WV>
+__device__ __forceinline__ void gram_slab(const T *st, int lane, typename Mfma<T>::acc *acc)
+{
+    constexpr int NT = W / 16;
+    constexpr int NUP = NT * (NT + 1) / 2;
+    constexpr int TPW = (NUP + 3) / 4;
+    const T *row = st + (lane / 16) * LDC + (lane % 16);
+    T cur[NT], nxt[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) cur[c] = row[c * 16];
+#pragma unroll
+    for (int k = 0; k < KR; k += 4) {
+        if (k + 4 < KR) {
+#pragma unroll
+            for (int c = 0; c < NT; ++c) nxt[c] = row[(k + 4) * LDC + c * 16];
+        }
+        static_assert(TPW <= 3, "tiles per wavefront");
+        acc[0] = mfma16x16x4(cur[GramTile<NT, WV, 0>::i], cur[GramTile<NT, WV, 0>::j], acc[0]);
+        if constexpr (TPW > 1)
+            acc[1] = mfma16x16x4(cur[GramTile<NT, WV, 1>::i], cur[GramTile<NT, WV, 1>::j], acc[1]);
+        if constexpr (TPW > 2)
+            acc[2] = mfma16x16x4(cur[GramTile<NT, WV, 2>::i], cur[GramTile<NT, WV, 2>::j], acc[2]);
+#pragma unroll
+        for (int c = 0; c < NT; ++c) cur[c] = nxt[c];
+    }
+}
+
 // 32-row slabs of G_P are staged transposed in LDS (row pitch W+1), double
 // buffered: the loads of slab s+1 are in flight in registers while the
-// MFMAs of slab s run, with one barrier per slab.
+// MFMAs of slab s run, with one barrier per slab.  Every wavefront runs the
+// same number of tiles (the upper tiles padded with repeats that are not
+// stored) and the tile indices are wave-uniform, so the k-loop has no
+// branches and the LDS reads of a slab overlap its MFMAs.  The step's
+// 1024 workgroups are resident at once only with four per CU, hence the
+// register budget of four wavefronts per SIMD (the LDS allows four too).
+// The block width b is W / 2 (the argument is kept for the launch shape).
 template <int W, class T>
-__global__ __launch_bounds__(256) void k_gram(const T *__restrict__ G, int m, long ldg, int b,
-                                              const int2 *__restrict__ piv, int rows_per_split,
-                                              double *__restrict__ partial)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gram(
+    const T *__restrict__ G, int m, long ldg, int b, const int2 *__restrict__ piv,
+    int rows_per_split, double *__restrict__ partial)
 {
     constexpr int KR = 32;                    // rows staged per slab
     constexpr int LDC = W + 1;                // padded LDS row (doubles)
@@ -88,74 +152,64 @@ __global__ __launch_bounds__(256) void k_gram(const T *__restrict__ G, int m, lo
     const int r_end = min(m, r_begin + rows_per_split);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    int ti[TPW], tj[TPW];
-#pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-        int t = wave + 4 * q, it = 0;
-        ti[q] = tj[q] = -1;
-        if (t < NUP) {
-            while (t >= NT - it) {               // row it of the upper triangle has NT - it tiles
-                t -= NT - it;
-                ++it;
-            }
-            ti[q] = it;
-            tj[q] = it + t;
-        }
-    }
+    // tile wave + 4 q of the upper triangle, row-major; past the last tile
+    // the wavefront repeats tile 0 and does not store it
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
     typename Mfma<T>::acc acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = typename Mfma<T>::acc{0, 0, 0, 0};
 
-    // element u of this thread's slab share: row kr = e % KR, column c = e / KR
-    const T *colp[EPT];
-    int kr_of[EPT], c_of[EPT];
+    // element u of this thread's slab share: row kr = tid % KR of pivot
+    // column c0 + CS u, c0 = tid / KR.  CS divides b = W / 2, so the column
+    // lies in block I for u < b / CS and in block J after: a wave-uniform
+    // column base per u plus one 32-bit per-lane offset.
+    constexpr int CS = 256 / KR;
+    constexpr int HB = W / 2;
+    static_assert(HB % CS == 0, "slab columns must not straddle the blocks");
+    const int kr = threadIdx.x % KR, c0 = threadIdx.x / KR;
+    const unsigned lane_off = (unsigned)c0 * (unsigned)ldg;
+    const T *colb[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
-        const int e = threadIdx.x + u * 256;
-        kr_of[u] = e % KR;
-        c_of[u] = e / KR;
-        colp[u] = G + (size_t)pivot_col(c_of[u], IJ, b) * ldg;
+        const int c = CS * u;
+        colb[u] = G + (size_t)(c < HB ? IJ.x * HB + c : IJ.y * HB + (c - HB)) * ldg;
     }
+    const int st_off = kr * LDC + c0;
+    // rows past r_end load row r_end - 1 (no branches) and are stored to
+    // LDS as zeros; the select sits at the store so that the loads of the
+    // next slab stay in flight across the MFMAs
     T reg[EPT];
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int r = r_begin + kr_of[u];
-        reg[u] = (r < r_end) ? colp[u][r] : T(0);
-    }
+    for (int u = 0; u < EPT; ++u) reg[u] = colb[u][lane_off + (unsigned)min(r_begin + kr, r_end - 1)];
     int buf = 0;
     for (int r0 = r_begin; r0 < r_end; r0 += KR) {
+        const bool live = r0 + kr < r_end;
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) st[buf][kr_of[u] * LDC + c_of[u]] = reg[u];
+        for (int u = 0; u < EPT; ++u) st[buf][st_off + CS * u] = live ? reg[u] : T(0);
         __syncthreads();
         const int r1 = r0 + KR;
         if (r1 < r_end) {
+            const unsigned rr = lane_off + (unsigned)min(r1 + kr, r_end - 1);
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) {
-                const int r = r1 + kr_of[u];
-                reg[u] = (r < r_end) ? colp[u][r] : T(0);
-            }
+            for (int u = 0; u < EPT; ++u) reg[u] = colb[u][rr];
         }
-#pragma unroll
-        for (int k = 0; k < KR; k += 4) {
-            const T *row = st[buf] + (k + lane / 16) * LDC + (lane % 16);
-#pragma unroll
-            for (int q = 0; q < TPW; ++q) {
-                if (ti[q] >= 0) {
-                    const T x = row[ti[q] * 16];
-                    const T y = row[tj[q] * 16];
-                    acc[q] = mfma16x16x4(x, y, acc[q]);
-                }
-            }
+        switch (wv) {
+        case 0: gram_slab<W, T, KR, LDC, 0>(st[buf], lane, acc); break;
+        case 1: gram_slab<W, T, KR, LDC, 1>(st[buf], lane, acc); break;
+        case 2: gram_slab<W, T, KR, LDC, 2>(st[buf], lane, acc); break;
+        default: gram_slab<W, T, KR, LDC, 3>(st[buf], lane, acc); break;
         }
         buf ^= 1;
     }
     double *out = partial + ((size_t)pv * gridDim.y + split) * W * W;
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
-        if (ti[q] < 0) continue;
+        const int t = wv + 4 * q;
+        if (t >= NUP) continue;
+        const int ti = upper_tile_i(NT, t), tj = upper_tile_j(NT, t);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = ti[q] * 16 + Mfma<T>::row(lane, r), col = tj[q] * 16 + lane % 16;
+            const int row = ti * 16 + Mfma<T>::row(lane, r), col = tj * 16 + lane % 16;
             out[(size_t)col * W + row] = (double)acc[q][r];
         }
     }
