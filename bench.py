@@ -610,10 +610,12 @@ def main():
     roofline = None
     kernels = None
     if not block and wl.ordering != 0 and kl[0]:
-        # nominal pair-stream bytes per launch: 32 (m + n) bytes per pair
+        # nominal pair-stream bytes per launch: 32 m bytes per pair for G, and
+        # 32 n for V rotated in the step or 16 for its rotation-log entry
         pairs_per_launch = P / n
         avg_ms = kms[0] / kl[0]
-        bytes_per_launch = pairs_per_launch * 32.0 * (m + n)
+        deferred = jevd.jevd_get_info(h).v_deferred
+        bytes_per_launch = pairs_per_launch * (32.0 * m + (16.0 if deferred else 32.0 * n))
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -622,6 +624,14 @@ def main():
                     "bytes_per_launch": bytes_per_launch,
                     "timing": "HIP events around each sweep's launches on the solver stream; "
                               "average includes dispatch gaps"}
+        if deferred and kl[3]:
+            # V read and written once per applied run of logged steps, plus the log
+            kernels = {"k_pair_step": {"ms_per_solve": round(kms[0] / args.steps, 3),
+                                       "launches_per_solve": kl[0] // args.steps,
+                                       "avg_us": round(1e3 * kms[0] / kl[0], 3)},
+                       "k_apply_vlog": {"ms_per_solve": round(kms[3] / args.steps, 3),
+                                        "launches_per_solve": kl[3] // args.steps,
+                                        "avg_us": round(1e3 * kms[3] / kl[3], 3)}}
     if block and kl[3]:
         npiv = N // 2
         # one update launch transforms G (m rows) and V (n rows) of all pivots

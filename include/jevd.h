@@ -108,7 +108,8 @@ enum {
     JEVD_K_PAIR_STEP = 0,    /* pointwise: one parallel step (or the one-workgroup solve) */
     JEVD_K_GRAM = 1,         /* block: pivot Grams G_P^T G_P */
     JEVD_K_PIVOT_SOLVE = 2,  /* block: Cholesky + inner sweeps per pivot */
-    JEVD_K_UPDATE = 3,       /* block: G_P <- G_P V_P and V(:,P) <- V(:,P) V_P */
+    JEVD_K_UPDATE = 3,       /* block: G_P <- G_P V_P and V(:,P) <- V(:,P) V_P;
+                                pointwise: V updated from the rotation log */
     JEVD_K_CLASSES = 4
 };
 typedef struct {
@@ -124,6 +125,9 @@ typedef struct {
     double kernel_ms[JEVD_K_CLASSES];
     long long kernel_launches[JEVD_K_CLASSES];
     int sweeps_low;    /* JEVD_PREC_MIXED: FP32 sweeps before the FP64 ones */
+    int v_deferred;    /* pointwise with V: 1 when the steps logged their rotations
+                          and V was updated from the log (timed as JEVD_K_UPDATE),
+                          0 when each step rotated its two columns of V */
 } jevd_info;
 
 /* Fills *o with the defaults listed above.  Never fails for a non-NULL o. */

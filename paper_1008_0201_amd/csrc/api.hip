@@ -58,6 +58,11 @@ struct jevd_handle_s {
     int *hsweeps = nullptr;  // pinned
     unsigned *dslots = nullptr;  // per-slot rotation / clamp counts of a sweep
     size_t capSlots = 0;
+    double2 *dvlog = nullptr;    // pointwise rotation log (deferred V update), two buffers
+    size_t capVlog = 0;
+    hipStream_t vstream = nullptr;   // second stream of the deferred V update
+    hipEvent_t evLogged[2] = {nullptr, nullptr};    // a log buffer is complete
+    hipEvent_t evApplied[2] = {nullptr, nullptr};   // V is updated from a log buffer
 
     // cached ordering table
     int tabN = -1, tabOrd = -1;
@@ -265,6 +270,15 @@ int jevd_destroy(jevd_handle_t h)
     if (h->dpairs) (void)hipFree(h->dpairs);
     if (h->dstep) (void)hipFree(h->dstep);
     if (h->dslots) (void)hipFree(h->dslots);
+    if (h->dvlog) (void)hipFree(h->dvlog);
+    if (h->vstream) {
+        (void)hipStreamSynchronize(h->vstream);
+        (void)hipStreamDestroy(h->vstream);
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (h->evLogged[i]) (void)hipEventDestroy(h->evLogged[i]);
+        if (h->evApplied[i]) (void)hipEventDestroy(h->evApplied[i]);
+    }
     if (h->vtmp) (void)hipFree(h->vtmp);
     if (h->adjK) (void)hipFree(h->adjK);
     if (h->adjW) (void)hipFree(h->adjW);
@@ -327,28 +341,97 @@ static int run_pointwise(jevd_handle_t h, int m, int n, double *G, int ldg, cons
     if (st) return st;
     HIP_TRY(hipMemsetAsync(h->dslots, 0, sizeof(unsigned) * 2 * nslots, h->stream));
     const long long pairs_per_sweep = h->hstep[nsteps];
+    // Deferred V: the steps log their rotations and V is updated once per
+    // run of logged steps (a whole sweep when the log fits kVlogMaxBytes),
+    // a few rows at a time in LDS, instead of its two columns being read and
+    // written by every step.  The updates go to a second stream, where they
+    // overlap the steps of the next run (the steps are latency-bound and
+    // leave most of the chip idle); two log buffers alternate, and a step
+    // that starts a run waits only for the update that last read its buffer.
+    // Every exit joins the second stream into the handle's stream.
+    const bool defer_v = V && vlog_rows(n) > 0 && nslots <= 16 * 256;
+    h->info.v_deferred = defer_v ? 1 : 0;
+    int chunk = 0;
+    if (defer_v) {
+        const size_t fit = kVlogMaxBytes / ((size_t)nslots * sizeof(double2));
+        chunk = (int)std::min<size_t>((size_t)nsteps, std::max<size_t>(1, fit));
+        chunk = std::min(chunk, kVlogMaxSteps);
+        st = grow_device(&h->dvlog, &h->capVlog, (size_t)2 * chunk * nslots);
+        if (st) return st;
+        if (!h->vstream) HIP_TRY(hipStreamCreateWithFlags(&h->vstream, hipStreamNonBlocking));
+        for (int i = 0; i < 2; ++i) {
+            if (!h->evLogged[i]) HIP_TRY(hipEventCreateWithFlags(&h->evLogged[i], hipEventDisableTiming));
+            if (!h->evApplied[i]) HIP_TRY(hipEventCreateWithFlags(&h->evApplied[i], hipEventDisableTiming));
+            // an earlier call that ended on an error may have left an update
+            // running on a buffer (an event never recorded is complete)
+            HIP_TRY(hipStreamWaitEvent(h->stream, h->evApplied[i], 0));
+        }
+    }
+    bool pending[2] = {false, false};   // an update from buffer b is enqueued
+    int runs = 0;
+    int result = JEVD_ENOCONV;
     for (int s = 0; s < o.max_sweeps; ++s) {
         // prefetch the V pair while more than a quarter of the pairs rotate
         const bool pf = s == 0 || 4 * (long long)h->hctr[s - 1].rotations > pairs_per_sweep;
-        // the launches of a sweep are timed as one group (no events between them)
+        // the step launches of a run (of a sweep without the log) are timed as
+        // one group (no events between them)
         HIP_TRY(h->timer.begin(h->stream, JEVD_K_PAIR_STEP));
+        int kc = 0, timed = 0;   // first step of the current run; launches in the group
+        double2 *logb = nullptr;
         for (int k = 0; k < nsteps; ++k) {
+            if (defer_v && k == kc) {
+                const int b = runs % 2;
+                if (pending[b]) HIP_TRY(hipStreamWaitEvent(h->stream, h->evApplied[b], 0));
+                logb = h->dvlog + (size_t)b * chunk * nslots;
+            }
             PairStepArgs a{G, m, (long)ldg, V, n, (long)ldv, h->dpairs + h->hstep[k],
                            h->hstep[k + 1] - h->hstep[k], dJ, tol, h->dctr + s, pf,
-                           h->dslots, h->dslots + nslots};
+                           h->dslots, h->dslots + nslots,
+                           defer_v ? logb + (size_t)(k - kc) * nslots : nullptr};
             HIP_TRY(launch_pair_step(a, h->stream));
+            ++timed;
+            if (defer_v && (k + 1 - kc == chunk || k + 1 == nsteps)) {
+                const int b = runs % 2;
+                HIP_TRY(h->timer.end(h->stream, timed));
+                timed = 0;
+                HIP_TRY(hipEventRecord(h->evLogged[b], h->stream));
+                HIP_TRY(hipStreamWaitEvent(h->vstream, h->evLogged[b], 0));
+                HIP_TRY(h->timer.begin(h->vstream, JEVD_K_UPDATE));
+                VlogApplyArgs va{V, n, n, (long)ldv, h->dpairs, h->dstep, kc, k + 1, logb,
+                                 nslots, h->maxPairsPerStep};
+                HIP_TRY(launch_apply_vlog(va, h->vstream));
+                HIP_TRY(h->timer.end(h->vstream, 1));
+                HIP_TRY(hipEventRecord(h->evApplied[b], h->vstream));
+                pending[b] = true;
+                ++runs;
+                kc = k + 1;
+                if (k + 1 < nsteps) HIP_TRY(h->timer.begin(h->stream, JEVD_K_PAIR_STEP));
+            }
         }
-        HIP_TRY(h->timer.end(h->stream, nsteps));
+        if (!defer_v) HIP_TRY(h->timer.end(h->stream, nsteps));
         HIP_TRY(launch_sum_slots(h->dslots, h->dslots + nslots, nslots, h->dctr + s, h->stream));
         HIP_TRY(hipMemcpyAsync(h->hctr + s, h->dctr + s, sizeof(SweepCounters), hipMemcpyDeviceToHost,
                                h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
-        HIP_TRY(h->timer.collect());
+        // with the second stream, the timings are collected once it has joined
+        if (!defer_v) HIP_TRY(h->timer.collect());
         *sweeps_done = s + 1;
-        if (h->hctr[s].nonfinite) return JEVD_ENONFINITE;
-        if (h->hctr[s].rotations == 0) return JEVD_OK;
+        if (h->hctr[s].nonfinite) {
+            result = JEVD_ENONFINITE;
+            break;
+        }
+        if (h->hctr[s].rotations == 0) {
+            result = JEVD_OK;
+            break;
+        }
     }
-    return JEVD_ENOCONV;
+    if (defer_v) {
+        for (int b = 0; b < 2; ++b)
+            if (pending[b]) HIP_TRY(hipStreamWaitEvent(h->stream, h->evApplied[b], 0));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        HIP_TRY(h->timer.collect());
+    }
+    return result;
 }
 
 int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed char *J, double tol,

@@ -690,54 +690,57 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
 // flight while the MFMAs of tile t run.
 constexpr int kUpdateTiles = 4;
 
-template <int W, class T>
-__global__ __launch_bounds__(256) void k_update(T *__restrict__ G, int m, long ldg,
-                                                T *__restrict__ V, int nv, long ldv, int b,
-                                                const int2 *__restrict__ piv,
-                                                const double *__restrict__ vpt,
-                                                const int *__restrict__ flag, int groups_g)
+// The row tiles of one k_update workgroup: V_P (W x W, FP64 row-major) is
+// staged in S (row pitch W + 16), then the wavefront transforms rows
+// wrow + lane % 16 + 64 t.  FULL: all rows of the workgroup exist, so no
+// load or store is predicated and the compiler waits for the prefetched
+// operands alone (a predicated memory operation leaves the count of those in
+// flight unknown, and it then waits for all of them, the stores included).
+// Otherwise the loads are clamped to the last row (the lanes past it only
+// feed result rows that are not stored) and the stores are guarded.
+template <int W, class T, bool FULL>
+__device__ __forceinline__ void update_tiles(T *__restrict__ X, long ld, int rows, int wrow,
+                                             int lane, int2 IJ, int b,
+                                             const double *__restrict__ src, T *S)
 {
     constexpr int KS = W / 4;   // k-steps of the MFMA
     constexpr int NT = W / 16;  // output column tiles
-    // V_P row-major with a row pitch of W + 16 doubles: the four 16-lane row
-    // groups of a fragment read then cover all 64 LDS banks in two cycles
     constexpr int SP = W + 16;
-    __shared__ T S[W * SP];
-    const int pv = blockIdx.y;
-    const bool is_v = (int)blockIdx.x >= groups_g;
-    const int f = flag[pv];
-    if (!(f == 1 || (is_v && f == 2))) return;   // flag 2: G_P already transformed
-    T *X = is_v ? V : G;
-    const long ld = is_v ? ldv : ldg;
-    const int rows = is_v ? nv : m;
-    const int2 IJ = piv[pv];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int group = is_v ? (int)blockIdx.x - groups_g : (int)blockIdx.x;
-    const int row0 = group * 64 * kUpdateTiles + wave * 16 + lane % 16;
-
-    const double *src = vpt + (size_t)pv * W * W;
-    for (int e = threadIdx.x; e < W * W; e += 256) S[(e / W) * SP + (e % W)] = (T)src[e];
+    constexpr int SE = W * W / 256;
+    auto clamp_row = [&](int r) { return FULL ? r : min(r, rows - 1); };
     // Pivot columns 4g .. 4g+3 lie in one block (b is a multiple of 4), so
     // the column of lane l in k-step ks is the wave-uniform pivot_col(4 ks)
     // plus l / 16: wave-uniform column bases and one 32-bit per-lane offset.
     const unsigned lane_off = (unsigned)(lane / 16) * (unsigned)ld;
+    const int row0 = wrow + lane % 16;
+
+    // all loads of V_P and of the first tile in flight before the LDS stores
+    double sv[SE];
+#pragma unroll
+    for (int i = 0; i < SE; ++i) sv[i] = src[threadIdx.x + 256 * i];
     T bf[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const T *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
-        bf[ks] = (row0 < rows) ? cb[lane_off + (unsigned)row0] : T(0);
+        bf[ks] = cb[lane_off + (unsigned)clamp_row(row0)];
+    }
+#pragma unroll
+    for (int i = 0; i < SE; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        S[(e / W) * SP + (e % W)] = (T)sv[i];
     }
     __syncthreads();
+#pragma unroll
     for (int t = 0; t < kUpdateTiles; ++t) {
         const int row = row0 + t * 64;
-        if (row - lane % 16 >= rows) break;   // the same for all lanes of the wavefront
+        if (!FULL && wrow + t * 64 >= rows) break;   // wave-uniform
         T nb[KS];
-        const int rn = row + 64;
-        const bool more = t + 1 < kUpdateTiles && rn < rows;
+        if (t + 1 < kUpdateTiles) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const T *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
-            nb[ks] = more ? cb[lane_off + (unsigned)rn] : T(0);
+            for (int ks = 0; ks < KS; ++ks) {
+                const T *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
+                nb[ks] = cb[lane_off + (unsigned)clamp_row(row + 64)];
+            }
         }
         typename Mfma<T>::acc acc[NT];
 #pragma unroll
@@ -752,7 +755,7 @@ __global__ __launch_bounds__(256) void k_update(T *__restrict__ G, int m, long l
 #pragma unroll
             for (int q = 0; q < NT; ++q) acc[q] = mfma16x16x4(srow[q * 16], bf[ks], acc[q]);
         }
-        if (row < rows) {
+        if (FULL || row < rows) {
             // element r of tile q is column q 16 + Mfma<T>::row(lane, r) of the
             // block pair (a 16-column tile lies inside one block: 16 | b)
 #pragma unroll
@@ -768,9 +771,41 @@ __global__ __launch_bounds__(256) void k_update(T *__restrict__ G, int m, long l
                     }
                 }
         }
+        if (t + 1 < kUpdateTiles) {
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) bf[ks] = nb[ks];
+            for (int ks = 0; ks < KS; ++ks) bf[ks] = nb[ks];
+        }
     }
+}
+
+template <int W, class T>
+__global__ __launch_bounds__(256) void k_update(T *__restrict__ G, int m, long ldg,
+                                                T *__restrict__ V, int nv, long ldv, int b,
+                                                const int2 *__restrict__ piv,
+                                                const double *__restrict__ vpt,
+                                                const int *__restrict__ flag, int groups_g)
+{
+    // V_P row-major with a row pitch of W + 16 doubles: the four 16-lane row
+    // groups of a fragment read then cover all 64 LDS banks in two cycles
+    constexpr int SP = W + 16;
+    __shared__ T S[W * SP];
+    const int pv = blockIdx.y;
+    const bool is_v = (int)blockIdx.x >= groups_g;
+    const int f = flag[pv];
+    if (!(f == 1 || (is_v && f == 2))) return;   // flag 2: G_P already transformed
+    T *X = is_v ? V : G;
+    const long ld = is_v ? ldv : ldg;
+    const int rows = is_v ? nv : m;
+    const int2 IJ = piv[pv];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int group = is_v ? (int)blockIdx.x - groups_g : (int)blockIdx.x;
+    const int wrow = group * 64 * kUpdateTiles + wave * 16;   // first row of the wavefront
+    const double *src = vpt + (size_t)pv * W * W;
+    if ((group + 1) * 64 * kUpdateTiles <= rows)   // the same for the whole workgroup
+        update_tiles<W, T, true>(X, ld, rows, wrow, lane, IJ, b, src, S);
+    else
+        update_tiles<W, T, false>(X, ld, rows, wrow, lane, IJ, b, src, S);
 }
 
 // ------------------------------------------------------------ host driver

@@ -24,7 +24,34 @@ struct PairStepArgs {
     bool prefetch_v;        // load the V pair with the G pair (most pairs rotate)
     unsigned *slot_rot;     // per workgroup slot: rotations in this sweep
     unsigned *slot_clamp;   // per workgroup slot: clamped hyperbolic transforms
+    double2 *vlog;          // this step's rotation log (npairs entries): V is
+                            // then left alone and updated by launch_apply_vlog;
+                            // null: V is rotated in the step
 };
+
+// Deferred V update: the logged rotations of steps k0 .. k1 - 1 (entries of
+// step k at vlog + (k - k0) * stride, pairs at pairs + step_start[k]).
+struct VlogApplyArgs {
+    double *V;
+    int nv, n;   // rows and columns of V
+    long ldv;
+    const int2 *pairs;       // device, all steps of the ordering
+    const int *step_start;   // device, nsteps + 1 offsets into pairs
+    int k0, k1;
+    const double2 *vlog;
+    int stride;              // entries per logged step (>= pairs of any step)
+    int max_pairs;           // pairs of the largest step (<= 4096)
+};
+// LDS for the rows of V held by one k_apply_vlog workgroup; the most log
+// kept before V is brought up to date.
+constexpr size_t kVlogLdsBytes = 128 * 1024;
+constexpr size_t kVlogMaxBytes = (size_t)64 << 20;
+// The most steps in one run of the log (their offsets also go to LDS).
+constexpr int kVlogMaxSteps = 4096;
+// Rows of V per k_apply_vlog workgroup for n columns (4 or 2; a column of
+// them takes one more double in LDS, and there are 256 scratch columns), or
+// 0 when even two rows do not fit (then V is rotated in the step).
+int vlog_rows(int n);
 
 struct SmallSolveArgs {
     double *G;
@@ -132,6 +159,7 @@ struct KernelTimer {
 };
 
 hipError_t launch_pair_step(const PairStepArgs &a, hipStream_t st);
+hipError_t launch_apply_vlog(const VlogApplyArgs &a, hipStream_t st);
 
 struct BatchInst;
 hipError_t launch_canonical(int batch, int m, int n, const double *lam, long long slam,

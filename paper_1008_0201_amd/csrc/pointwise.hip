@@ -5,6 +5,10 @@
 //                      pass and the rotation pass (m <= BS * CH).
 //   k_pair_step_stream the same for taller columns: the columns are read
 //                      twice (Gram pass, rotation pass).
+//   k_apply_vlog       the deferred V update: with a rotation log the step
+//                      kernels leave V alone and record each pair's (c, s);
+//                      this kernel then applies a run of logged steps to a
+//                      few rows of V held in LDS.
 //   k_small_solve      a whole solve (all sweeps) of a small problem in one
 //                      workgroup, with G and V resident in LDS; used for the
 //                      row-cyclic ordering, whose pairs are strictly
@@ -44,6 +48,14 @@ __device__ __forceinline__ void rotate_columns(double *__restrict__ vp, double *
     }
 }
 
+// One entry of the rotation log: (c, s) of the pair's transform, with c
+// negated for a hyperbolic one (c = cos or cosh is positive, so the sign is
+// free); (1, 0) for a pair that does not rotate (the identity, exactly).
+__device__ __forceinline__ double2 log_entry(double c, double s, bool same)
+{
+    return make_double2(same ? c : -c, s);
+}
+
 // PF: the V pair (nv <= BS * CH rows) is loaded together with the G pair,
 // before the rotation decision, so that both loads are in flight at once;
 // worth it when most pairs of the sweep rotate.
@@ -54,7 +66,8 @@ __global__ __launch_bounds__(BS) void k_pair_step(double *__restrict__ G, int m,
                                                   const signed char *__restrict__ J, double tol,
                                                   SweepCounters *__restrict__ ctr,
                                                   unsigned *__restrict__ slot_rot,
-                                                  unsigned *__restrict__ slot_clamp)
+                                                  unsigned *__restrict__ slot_clamp,
+                                                  double2 *__restrict__ vlog)
 {
     __shared__ double sh[3 * BS / kWave];
     const int2 pq = pairs[blockIdx.x];
@@ -89,13 +102,20 @@ __global__ __launch_bounds__(BS) void k_pair_step(double *__restrict__ G, int m,
     }
     block_sum3<BS>(app, aqq, apq, sh);
     if (!finite3(app, aqq, apq)) {
-        if (threadIdx.x == 0) ctr->nonfinite = 1u;
+        if (threadIdx.x == 0) {
+            ctr->nonfinite = 1u;
+            if (vlog) vlog[blockIdx.x] = make_double2(1.0, 0.0);
+        }
         return;
     }
-    if (!needs_rotation(app, aqq, apq, tol)) return;
+    if (!needs_rotation(app, aqq, apq, tol)) {
+        if (vlog && threadIdx.x == 0) vlog[blockIdx.x] = make_double2(1.0, 0.0);
+        return;
+    }
     const bool same = (J == nullptr) || (J[pq.x] == J[pq.y]);
     double c, s;
     const bool clamped = transform_params(app, aqq, apq, same, c, s);
+    if (vlog && threadIdx.x == 0) vlog[blockIdx.x] = log_entry(c, s, same);
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
         const int r = threadIdx.x + k * BS;
@@ -135,7 +155,8 @@ __global__ __launch_bounds__(BS) void k_pair_step_stream(double *__restrict__ G,
                                                          const signed char *__restrict__ J,
                                                          double tol, SweepCounters *__restrict__ ctr,
                                                          unsigned *__restrict__ slot_rot,
-                                                         unsigned *__restrict__ slot_clamp)
+                                                         unsigned *__restrict__ slot_clamp,
+                                                         double2 *__restrict__ vlog)
 {
     __shared__ double sh[3 * BS / kWave];
     const int2 pq = pairs[blockIdx.x];
@@ -150,18 +171,126 @@ __global__ __launch_bounds__(BS) void k_pair_step_stream(double *__restrict__ G,
     }
     block_sum3<BS>(app, aqq, apq, sh);
     if (!finite3(app, aqq, apq)) {
-        if (threadIdx.x == 0) ctr->nonfinite = 1u;
+        if (threadIdx.x == 0) {
+            ctr->nonfinite = 1u;
+            if (vlog) vlog[blockIdx.x] = make_double2(1.0, 0.0);
+        }
         return;
     }
-    if (!needs_rotation(app, aqq, apq, tol)) return;
+    if (!needs_rotation(app, aqq, apq, tol)) {
+        if (vlog && threadIdx.x == 0) vlog[blockIdx.x] = make_double2(1.0, 0.0);
+        return;
+    }
     const bool same = (J == nullptr) || (J[pq.x] == J[pq.y]);
     double c, s;
     const bool clamped = transform_params(app, aqq, apq, same, c, s);
+    if (vlog && threadIdx.x == 0) vlog[blockIdx.x] = log_entry(c, s, same);
     rotate_columns<BS>(gp, gq, m, c, s, same);
     if (V) rotate_columns<BS>(V + (size_t)pq.x * ldv, V + (size_t)pq.y * ldv, nv, c, s, same);
     if (threadIdx.x == 0) {
         slot_rot[blockIdx.x] += 1u;
         if (clamped) slot_clamp[blockIdx.x] += 1u;
+    }
+}
+
+// ------------------------------------------------------------ k_apply_vlog
+// Rows RB b .. RB b + RB - 1 of V (all n columns, sv[col * (RB + 1) + r]:
+// the padding spreads the columns that the lanes of a wavefront touch over
+// the LDS banks, where a pitch of RB doubles left them on eight) go to LDS,
+// with RB scratch values per thread and the run's step offsets (so that no
+// scalar memory load sits on a step's path); the logged rotations of steps k0 .. k1 - 1 are applied to them in
+// step order, so every element of V sees the same rotations in the same
+// order (and the same arithmetic, rotate_elems) as an in-step update.  A
+// thread takes pairs tid, tid + 256, ... of a step (PPT of them at most) and
+// all RB rows of each, one barrier per step.  The log entries and pair
+// indices of the next D steps are in flight in registers (a ring of D slots,
+// refilled as each step is done; past k1 - 1 the last step is loaded again,
+// so that no load is predicated): a step's LDS work is far shorter than the
+// latency of the log's loads.
+template <int RB, int PPT>
+__global__ __launch_bounds__(256) void k_apply_vlog(double *__restrict__ V, int nv, int n, long ldv,
+                                                    const int2 *__restrict__ pairs,
+                                                    const int *__restrict__ step_start, int k0,
+                                                    int k1, const double2 *__restrict__ vlog,
+                                                    int stride)
+{
+    constexpr int D = PPT >= 16 ? 1 : 16 / PPT;
+    // n columns of V rows, a scratch column per thread (pitch CP), the
+    // offsets of steps k0 .. k1 into the pair table
+    constexpr int CP = RB + 1;
+    extern __shared__ double sv[];
+    double *mine = sv + (size_t)(n + threadIdx.x) * CP;
+    int *ss = (int *)(sv + (size_t)(n + 256) * CP);
+    for (int k = k0 + (int)threadIdx.x; k <= k1; k += 256) ss[k - k0] = step_start[k];
+    __syncthreads();
+    const int row0 = blockIdx.x * RB;
+    const int nr = min(RB, nv - row0);
+    double2 cs[D][PPT];
+    int2 pq[D][PPT];
+    int np[D];
+    auto fetch = [&](int k, double2 *c_out, int2 *p_out, int &np_out) {
+        const int s0 = ss[k - k0];
+        np_out = ss[k - k0 + 1] - s0;
+        const double2 *lg = vlog + (size_t)(k - k0) * stride;
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            // in bounds also for a step without pairs (entry 0 is read, unused)
+            const int p = max(0, min((int)threadIdx.x + 256 * i, np_out - 1));
+            c_out[i] = lg[p];
+            p_out[i] = pairs[np_out > 0 ? s0 + p : 0];
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < D; ++j) fetch(min(k0 + j, k1 - 1), cs[j], pq[j], np[j]);
+    // V rows: eight loads in flight per thread (clamped indices), then LDS
+    const int ne = n * RB;
+    for (int e0 = 0; e0 < ne; e0 += 8 * 256) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = min(e0 + (int)threadIdx.x + 256 * u, ne - 1);
+            t[u] = V[(size_t)(e / RB) * ldv + row0 + min(e % RB, nr - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + (int)threadIdx.x + 256 * u;
+            if (e < ne) sv[(e / RB) * CP + e % RB] = (e % RB < nr) ? t[u] : 0.0;
+        }
+    }
+    __syncthreads();
+    for (int kb = k0; kb < k1; kb += D) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const int k = kb + j;
+            if (k >= k1) break;   // the same for the whole workgroup
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                // no branch: a lane without a rotation (past the step's pairs,
+                // or the identity, s = 0) works on its own scratch rows, so
+                // that the slot's loads are consumed on every path and the
+                // compiler keeps the later slots in flight when it refills
+                // this one
+                const int p = (int)threadIdx.x + 256 * i;
+                const bool act = p < np[j] && cs[j][i].y != 0.0;
+                const bool same = cs[j][i].x > 0.0;
+                const double c = fabs(cs[j][i].x), s = cs[j][i].y;
+                double *a = act ? sv + pq[j][i].x * CP : mine;
+                double *b = act ? sv + pq[j][i].y * CP : mine;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    double x = a[r], y = b[r];
+                    rotate_elems(x, y, c, s, same);
+                    a[r] = x;
+                    b[r] = y;
+                }
+            }
+            __syncthreads();
+            fetch(min(k + D, k1 - 1), cs[j], pq[j], np[j]);
+        }
+    }
+    for (int e = threadIdx.x; e < n * RB; e += 256) {
+        const int col = e / RB, r = e % RB;
+        if (r < nr) V[(size_t)col * ldv + row0 + r] = sv[col * CP + r];
     }
 }
 
@@ -430,12 +559,15 @@ template <int BS, int CH>
 static void launch_ch(const PairStepArgs &a, hipStream_t st)
 {
     dim3 grid(a.npairs), block(BS);
-    if (a.prefetch_v && a.V && a.nv <= BS * CH)
-        k_pair_step<BS, CH, true><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs,
-                                                          a.J, a.tol, a.ctr, a.slot_rot, a.slot_clamp);
+    double *V = a.vlog ? nullptr : a.V;   // with a log, V is updated later
+    if (a.prefetch_v && V && a.nv <= BS * CH)
+        k_pair_step<BS, CH, true><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, V, a.nv, a.ldv, a.pairs,
+                                                          a.J, a.tol, a.ctr, a.slot_rot, a.slot_clamp,
+                                                          a.vlog);
     else
-        k_pair_step<BS, CH, false><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv, a.pairs,
-                                                           a.J, a.tol, a.ctr, a.slot_rot, a.slot_clamp);
+        k_pair_step<BS, CH, false><<<grid, block, 0, st>>>(a.G, a.m, a.ldg, V, a.nv, a.ldv, a.pairs,
+                                                           a.J, a.tol, a.ctr, a.slot_rot, a.slot_clamp,
+                                                           a.vlog);
 }
 
 template <int BS>
@@ -453,9 +585,9 @@ static hipError_t launch_pair_step_bs(const PairStepArgs &a, hipStream_t st)
     else if (ch <= 16)
         launch_ch<BS, 16>(a, st);
     else
-        k_pair_step_stream<BS><<<dim3(a.npairs), dim3(BS), 0, st>>>(a.G, a.m, a.ldg, a.V, a.nv, a.ldv,
-                                                                    a.pairs, a.J, a.tol, a.ctr,
-                                                                    a.slot_rot, a.slot_clamp);
+        k_pair_step_stream<BS><<<dim3(a.npairs), dim3(BS), 0, st>>>(
+            a.G, a.m, a.ldg, a.vlog ? nullptr : a.V, a.nv, a.ldv, a.pairs, a.J, a.tol, a.ctr,
+            a.slot_rot, a.slot_clamp, a.vlog);
     return hipGetLastError();
 }
 
@@ -507,6 +639,51 @@ hipError_t launch_small_solve(const SmallSolveArgs &a, hipStream_t st)
     if (a.max_pairs_per_step <= 4) return launch_small_nw<4>(a, st);
     if (a.max_pairs_per_step <= 8) return launch_small_nw<8>(a, st);
     return launch_small_nw<16>(a, st);
+}
+
+int vlog_rows(int n)
+{
+    if ((size_t)5 * (n + 256) * sizeof(double) <= kVlogLdsBytes) return 4;
+    if ((size_t)3 * (n + 256) * sizeof(double) <= kVlogLdsBytes) return 2;
+    return 0;
+}
+
+template <int RB, int PPT>
+static hipError_t launch_apply_rb(const VlogApplyArgs &a, hipStream_t st)
+{
+    const size_t bytes = (size_t)(RB + 1) * (a.n + 256) * sizeof(double) +
+                         (size_t)(a.k1 - a.k0 + 1) * sizeof(int);
+    if (bytes > 160 * 1024) return hipErrorInvalidValue;
+    if (bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_apply_vlog<RB, PPT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    const int grid = (a.nv + RB - 1) / RB;
+    k_apply_vlog<RB, PPT><<<grid, 256, bytes, st>>>(a.V, a.nv, a.n, a.ldv, a.pairs, a.step_start,
+                                                    a.k0, a.k1, a.vlog, a.stride);
+    return hipGetLastError();
+}
+
+template <int RB>
+static hipError_t launch_apply_ppt(const VlogApplyArgs &a, hipStream_t st)
+{
+    const int ppt = (a.max_pairs + 255) / 256;
+    if (ppt <= 1) return launch_apply_rb<RB, 1>(a, st);
+    if (ppt <= 2) return launch_apply_rb<RB, 2>(a, st);
+    if (ppt <= 4) return launch_apply_rb<RB, 4>(a, st);
+    if (ppt <= 8) return launch_apply_rb<RB, 8>(a, st);
+    return launch_apply_rb<RB, 16>(a, st);
+}
+
+hipError_t launch_apply_vlog(const VlogApplyArgs &a, hipStream_t st)
+{
+    if (a.k1 <= a.k0 || a.nv <= 0) return hipSuccess;
+    if (a.max_pairs > 16 * 256) return hipErrorInvalidValue;
+    const int rb = vlog_rows(a.n);
+    if (rb == 4) return launch_apply_ppt<4>(a, st);
+    if (rb == 2) return launch_apply_ppt<2>(a, st);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_sum_slots(unsigned *slot_rot, unsigned *slot_clamp, int nslots,

@@ -139,6 +139,11 @@ def test_opts_struct_matches_header():
     opts = hdr[hdr.index("typedef struct {"):hdr.index("} jevd_opts;")]
     fields = re.findall(r"^\s+int (\w+);", opts, re.M)
     assert fields == [f for f, _ in B.jevd_opts._fields_]
+    start = hdr.index("typedef struct {", hdr.index("JEVD_INFO_MAX_SWEEPS"))
+    info = hdr[start:hdr.index("} jevd_info;")]
+    info = re.sub(r"/\*.*?\*/", "", info, flags=re.S)
+    names = re.findall(r"^\s+(?:int|long long|double) (\w+)(?:\[\w+\])?;", info, re.M)
+    assert names == [f for f, _ in B.jevd_info._fields_]
     o = B.jevd_default_opts()
     assert (o.ordering, o.variant, o.block, o.max_sweeps, o.max_inner, o.accumulate_v, o.pivot,
             o.precision) == (B.ORD_MODMODULUS, B.VAR_AUTO, 0, 50, 30, 0, B.PIVOT_NONE, B.PREC_FP64)

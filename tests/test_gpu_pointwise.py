@@ -177,3 +177,26 @@ def test_u_aliases_g(solver, orc):
     assert np.max(np.abs(Uv.T @ Uv - np.eye(140))) <= 10 * 140 * EPS
     ref = orc.jevd(wl.G, wl.J, wl.tol, W.MODMODULUS, want_v=False)
     assert rel_err(host(lam), ref.lam) <= REL_TOL
+
+
+@pytest.mark.parametrize("n,indef", [(3000, True), (4200, False)])
+def test_deferred_v_in_several_log_runs(solver, n, indef):
+    """V updated from the rotation log: at n = 3000 (four rows of V per
+    workgroup) a sweep's log exceeds its 64 MiB cap and is applied in two
+    runs, at n = 4200 (two rows per workgroup) in three.  G's iteration must
+    not depend on V (the same lambda, bit for bit, and the same rotation
+    counts as without V), V^T J V = J and G_out = G_in V (products in FP64,
+    whose error is within the bound)."""
+    wl = W.graded_hyperbolic(n, k=300 + n, grade=1.0)
+    J = wl.J if indef else None
+    got = run_gpu(solver, wl.G, J, wl.tol, W.MODMODULUS)
+    nov = run_gpu(solver, wl.G, J, wl.tol, W.MODMODULUS, want_V=False)
+    assert got["st"] == 0 and nov["st"] == 0
+    assert got["sweeps"] == nov["sweeps"] and got["rot"] == nov["rot"]
+    assert np.array_equal(got["lam"], nov["lam"])
+    jj = np.ones(n) if J is None else np.asarray(J, dtype=float)
+    V = got["V"]
+    vmax = np.max(np.sum(V * V, axis=0))
+    assert np.max(np.abs(V.T @ (jj[:, None] * V) - np.diag(jj))) <= 10 * n * EPS * vmax
+    scale = np.sqrt(np.sum((np.abs(wl.G) @ np.abs(V)) ** 2, axis=0))
+    assert np.max(np.abs(wl.G @ V - got["G"]).sum(axis=0) / scale) <= 100 * n * EPS
