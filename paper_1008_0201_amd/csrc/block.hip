@@ -734,6 +734,9 @@ __device__ __forceinline__ void update_tiles(T *__restrict__ X, long ld, int row
     for (int t = 0; t < kUpdateTiles; ++t) {
         const int row = row0 + t * 64;
         if (!FULL && wrow + t * 64 >= rows) break;   // wave-uniform
+        // no instruction: keeps the V_P reads of each tile in its tile (merged
+        // across the unrolled tiles they would hold 128 registers throughout)
+        asm volatile("" ::: "memory");
         T nb[KS];
         if (t + 1 < kUpdateTiles) {
 #pragma unroll
@@ -745,11 +748,8 @@ __device__ __forceinline__ void update_tiles(T *__restrict__ X, long ld, int row
         typename Mfma<T>::acc acc[NT];
 #pragma unroll
         for (int q = 0; q < NT; ++q) acc[q] = typename Mfma<T>::acc{0, 0, 0, 0};
-        // partly unrolled: fully unrolled, the V_P fragments of all k-steps
-        // are hoisted into registers (198 VGPRs, two wavefronts per SIMD);
-        // two passes of eight k-steps keep three resident and measured
-        // 10 % faster at n = 8192
-#pragma unroll 8
+        // fully unrolled (a rolled k-loop indexes bf[] at run time)
+#pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const T *srow = S + (4 * ks + lane / 16) * SP + (lane % 16);
 #pragma unroll
