@@ -91,6 +91,19 @@ __host__ __device__ constexpr int upper_tile_j(int NT, int t)
 // the upper triangle (past the last tile, tile 0 again), all indices known at
 // compile time.  Each k-step reads the NT column-block operands once; the
 // reads of step k + 1 are issued before the MFMAs of step k.
+// x, or +0 when !keep, without a branch (an all-ones or all-zeros mask on
+// the bits).
+__device__ __forceinline__ double zero_unless(double x, bool keep)
+{
+    const long long m = -(long long)keep;
+    return __longlong_as_double(__double_as_longlong(x) & m);
+}
+__device__ __forceinline__ float zero_unless(float x, bool keep)
+{
+    const int m = -(int)keep;
+    return __int_as_float(__float_as_int(x) & m);
+}
+
 template <int NT, int WV, int Q>
 struct GramTile {
     static constexpr int t = (WV + 4 * Q < NT * (NT + 1) / 2) ? WV + 4 * Q : 0;
@@ -126,8 +139,8 @@ __device__ __forceinline__ void gram_slab(const T *st, int lane, typename Mfma<T
 }
 
 // 32-row slabs of G_P are staged transposed in LDS (row pitch W+1), double
-// buffered: the loads of slab s+1 are in flight in registers while the
-// MFMAs of slab s run, with one barrier per slab.  Every wavefront runs the
+// buffered: the loads of slabs s+1 and s+2 are in flight in registers while
+// the MFMAs of slab s run, with one barrier per slab.  Every wavefront runs the
 // same number of tiles (the upper tiles padded with repeats that are not
 // stored) and the tile indices are wave-uniform, so the k-loop has no
 // branches and the LDS reads of a slab overlap its MFMAs.  The step's
@@ -175,31 +188,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         colb[u] = G + (size_t)(c < HB ? IJ.x * HB + c : IJ.y * HB + (c - HB)) * ldg;
     }
     const int st_off = kr * LDC + c0;
-    // rows past r_end load row r_end - 1 (no branches) and are stored to
-    // LDS as zeros; the select sits at the store so that the loads of the
-    // next slab stay in flight across the MFMAs
-    T reg[EPT];
+    // Two slabs of loads in flight: register sets ra and rb take alternate
+    // slabs, and a set is refilled with the slab two ahead as soon as it has
+    // gone to LDS.  Rows past r_end load row r_end - 1 (no predicated load:
+    // every lane of a column then reads one line) and are stored to LDS as
+    // zeros; the select sits at the store, so that the loads stay in flight
+    // across the MFMAs.
+    auto load_slab = [&](T *reg, int r0) {
+        const unsigned rr = lane_off + (unsigned)min(r0 + kr, r_end - 1);
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) reg[u] = colb[u][lane_off + (unsigned)min(r_begin + kr, r_end - 1)];
-    int buf = 0;
-    for (int r0 = r_begin; r0 < r_end; r0 += KR) {
+        for (int u = 0; u < EPT; ++u) reg[u] = colb[u][rr];
+    };
+    auto run_slab = [&](T *reg, int r0, int buf) {
+        // zeroing by a bit mask: a select here was turned into a branch
+        // around the store, which left the loads counted as in flight
         const bool live = r0 + kr < r_end;
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) st[buf][st_off + CS * u] = live ? reg[u] : T(0);
+        for (int u = 0; u < EPT; ++u) st[buf][st_off + CS * u] = zero_unless(reg[u], live);
         __syncthreads();
-        const int r1 = r0 + KR;
-        if (r1 < r_end) {
-            const unsigned rr = lane_off + (unsigned)min(r1 + kr, r_end - 1);
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) reg[u] = colb[u][rr];
-        }
+        load_slab(reg, r0 + 2 * KR);
         switch (wv) {
         case 0: gram_slab<W, T, KR, LDC, 0>(st[buf], lane, acc); break;
         case 1: gram_slab<W, T, KR, LDC, 1>(st[buf], lane, acc); break;
         case 2: gram_slab<W, T, KR, LDC, 2>(st[buf], lane, acc); break;
         default: gram_slab<W, T, KR, LDC, 3>(st[buf], lane, acc); break;
         }
-        buf ^= 1;
+    };
+    T ra[EPT], rb[EPT];
+    load_slab(ra, r_begin);
+    load_slab(rb, r_begin + KR);
+    for (int r0 = r_begin; r0 < r_end; r0 += 2 * KR) {
+        run_slab(ra, r0, 0);
+        if (r0 + KR >= r_end) break;   // the same for the whole workgroup
+        run_slab(rb, r0 + KR, 1);
     }
     double *out = partial + ((size_t)pv * gridDim.y + split) * W * W;
 #pragma unroll
