@@ -336,12 +336,13 @@ struct PivotSolveArgs {
 template <int W>
 constexpr int gram_pitch() { return W + 1; }
 
-// Workgroup of the pivot solve: 4 wavefronts.  In the inner sweeps lane k of
-// every wavefront owns pair k of the step (W/2 pairs) and wavefront w owns
-// rows [w W/4, (w+1) W/4) of R and V_P: each wavefront forms partial dot
-// products over its rows, the partials meet in LDS, and every wavefront adds
-// them in wavefront order (identical totals everywhere) and computes the
-// 2x2 transforms of all pairs at once, one per lane, before rotating its rows.
+// Workgroup of the pivot solve: 4 wavefronts.  In the inner sweeps lanes 2k
+// and 2k + 1 of every wavefront own pair k of the step (W/2 pairs), each half
+// of the wavefront's rows [w W/4, (w+1) W/4) of R and V_P: the two lanes
+// add their partial dot products (one DPP swap), the wavefronts' partials
+// meet in LDS, and every wavefront adds them in wavefront order (identical
+// totals everywhere) and computes the 2x2 transforms of all pairs at once
+// before each lane rotates its rows.
 constexpr int kPivotThreads = 256;
 
 template <int W>
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     constexpr int P = gram_pitch<W>();
     constexpr int NP = W / 2;          // pairs per inner step
     constexpr int RPW = W / NW;        // rows of R / V_P per wavefront
-    static_assert(NP <= 64, "one pair per lane");
+    static_assert(NP <= 32, "two lanes per pair");
     extern __shared__ double lds[];
     double *A = lds;                   // W x W column-major, pitch P: Gram, then R
     double *VP = lds + W * P;          // W x W column-major, pitch P (first: rows of R)
@@ -565,61 +566,70 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     }
     __syncthreads();
     const int sweeps = a.full_block ? a.max_inner : 1;
-    const int r0w = wave * RPW;
+    constexpr int HR = RPW / 2;                 // rows per lane in an inner step
+    const int pk = lane >> 1, half = lane & 1;  // the lane's pair and half
+    const int r0h = wave * RPW + half * HR;
     for (int it = 0; it < sweeps; ++it) {
         unsigned long long rot_it = 0;
         if (!broke) {
             const int nsteps = inner_steps(a.all_pairs, W);
             for (int s = 0; s < nsteps; ++s) {
+                // two lanes per pair: lane 2k + h takes rows [h HR, (h+1) HR)
+                // of this wavefront's rows of pair k
+                const bool mine = pk < NP;
                 int2 pq = make_int2(0, 1);
-                if (lane < NP) pq = inner_pair(a.all_pairs, W, s, lane);
-                double *yp = A + pq.x * P + r0w, *yq = A + pq.y * P + r0w;
-                // this wavefront's rows of the pair stay in registers until
-                // the rotation (no other wavefront touches them in the step)
-                double xr[RPW], yr[RPW];
+                if (mine) pq = inner_pair(a.all_pairs, W, s, pk);
+                double *yp = A + pq.x * P + r0h, *yq = A + pq.y * P + r0h;
+                // this lane's rows of the pair stay in registers until the
+                // rotation (no other lane touches them in the step)
+                double xr[HR], yr[HR];
 #pragma unroll
-                for (int r = 0; r < RPW; ++r) {
+                for (int r = 0; r < HR; ++r) {
                     xr[r] = yp[r];
                     yr[r] = yq[r];
                 }
-                // partial dot products over this wavefront's rows, added as a
-                // pairwise tree (rounding grows with log2(RPW), not RPW)
-                double sxx[RPW], syy[RPW], sxy[RPW];
+                // partial dot products over this lane's rows, added as a
+                // pairwise tree (rounding grows with log2(HR), not HR), then
+                // the two lanes of the pair add theirs (x + y = y + x: both
+                // lanes hold the same sum)
+                double sxx[HR], syy[HR], sxy[HR];
 #pragma unroll
-                for (int r = 0; r < RPW; ++r) {
+                for (int r = 0; r < HR; ++r) {
                     sxx[r] = xr[r] * xr[r];
                     syy[r] = yr[r] * yr[r];
                     sxy[r] = xr[r] * yr[r];
                 }
 #pragma unroll
-                for (int h = RPW / 2; h > 0; h /= 2)
+                for (int h = HR / 2; h > 0; h /= 2)
 #pragma unroll
                     for (int r = 0; r < h; ++r) {
                         sxx[r] += sxx[r + h];
                         syy[r] += syy[r + h];
                         sxy[r] += sxy[r + h];
                     }
-                double app = sxx[0], aqq = syy[0], apq = sxy[0];
-                if (lane < NP) {
-                    red[(wave * 3 + 0) * NP + lane] = app;
-                    red[(wave * 3 + 1) * NP + lane] = aqq;
-                    red[(wave * 3 + 2) * NP + lane] = apq;
+                double app = sxx[0] + dpp_move<0xB1>(sxx[0]);
+                double aqq = syy[0] + dpp_move<0xB1>(syy[0]);
+                double apq = sxy[0] + dpp_move<0xB1>(sxy[0]);
+                if (mine && half == 0) {
+                    red[(wave * 3 + 0) * NP + pk] = app;
+                    red[(wave * 3 + 1) * NP + pk] = aqq;
+                    red[(wave * 3 + 2) * NP + pk] = apq;
                 }
                 __syncthreads();
                 app = aqq = apq = 0.0;
-                if (lane < NP) {
+                if (mine) {
                     // (w0 + w1) + (w2 + w3): the same order in every wavefront
                     static_assert(NW == 4, "four wavefronts");
                     double t[3][NW];
 #pragma unroll
                     for (int w = 0; w < NW; ++w)
 #pragma unroll
-                        for (int k = 0; k < 3; ++k) t[k][w] = red[(w * 3 + k) * NP + lane];
+                        for (int k = 0; k < 3; ++k) t[k][w] = red[(w * 3 + k) * NP + pk];
                     app = (t[0][0] + t[0][1]) + (t[0][2] + t[0][3]);
                     aqq = (t[1][0] + t[1][1]) + (t[1][2] + t[1][3]);
                     apq = (t[2][0] + t[2][1]) + (t[2][2] + t[2][3]);
                 }
-                bool act = lane < NP;
+                bool act = mine;
                 if (act && !finite3(app, aqq, apq)) {
                     bad = 1;
                     act = false;
@@ -627,30 +637,30 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
                 act = act && needs_rotation(app, aqq, apq, a.tol);
                 const bool same = act ? (JI[pq.x] == JI[pq.y]) : true;
                 double c = 1.0, sn = 0.0;
-                if (act && transform_params(app, aqq, apq, same, c, sn) && wave == 0) ++ncl;
+                if (act && transform_params(app, aqq, apq, same, c, sn) && wave == 0 && half == 0) ++ncl;
                 if (act) {
                     // all loads first, then the arithmetic, then the stores:
                     // one LDS latency instead of one per row
-                    double *vp = VP + pq.x * P + r0w, *vq = VP + pq.y * P + r0w;
-                    double vx[RPW], vy[RPW];
+                    double *vp = VP + pq.x * P + r0h, *vq = VP + pq.y * P + r0h;
+                    double vx[HR], vy[HR];
 #pragma unroll
-                    for (int r = 0; r < RPW; ++r) {
+                    for (int r = 0; r < HR; ++r) {
                         vx[r] = vp[r];
                         vy[r] = vq[r];
                     }
 #pragma unroll
-                    for (int r = 0; r < RPW; ++r) {
+                    for (int r = 0; r < HR; ++r) {
                         rotate_elems(xr[r], yr[r], c, sn, same);
                         rotate_elems(vx[r], vy[r], c, sn, same);
                     }
 #pragma unroll
-                    for (int r = 0; r < RPW; ++r) {
+                    for (int r = 0; r < HR; ++r) {
                         yp[r] = xr[r];
                         yq[r] = yr[r];
                         vp[r] = vx[r];
                         vq[r] = vy[r];
                     }
-                    if (wave == 0) ++rot_it;
+                    if (wave == 0 && half == 0) ++rot_it;
                 }
                 __syncthreads();
             }

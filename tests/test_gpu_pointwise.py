@@ -200,3 +200,30 @@ def test_deferred_v_in_several_log_runs(solver, n, indef):
     assert np.max(np.abs(V.T @ (jj[:, None] * V) - np.diag(jj))) <= 10 * n * EPS * vmax
     scale = np.sqrt(np.sum((np.abs(wl.G) @ np.abs(V)) ** 2, axis=0))
     assert np.max(np.abs(wl.G @ V - got["G"]).sum(axis=0) / scale) <= 100 * n * EPS
+
+
+def test_deferred_v_exits(solver):
+    """The exits of the multi-launch path with V updated from the rotation
+    log: after max_sweeps (ENOCONV) V is complete and consistent with the
+    iterate (G_out = G_in V); a NaN input gives ENONFINITE; the next solve on
+    the same handle is unaffected (the same result as on a fresh handle)."""
+    from paper_1008_0201_amd import jevd
+    n = 300
+    wl = W.graded_hyperbolic(n, k=77, grade=1.5)
+    got = run_gpu(solver, wl.G, wl.J, wl.tol, W.MODMODULUS, max_sweeps=2)
+    assert got["st"] == -3 and got["sweeps"] == 2
+    assert got["info"].v_deferred == 1
+    V = got["V"]
+    scale = np.sqrt(np.sum((np.abs(wl.G) @ np.abs(V)) ** 2, axis=0))
+    assert np.max(np.abs(wl.G @ V - got["G"]).sum(axis=0) / scale) <= 100 * n * EPS
+    bad = wl.G.copy()
+    bad[7, 11] = np.nan
+    assert run_gpu(solver, bad, wl.J, wl.tol, W.MODMODULUS)["st"] == -2
+    again = run_gpu(solver, wl.G, wl.J, wl.tol, W.MODMODULUS)
+    fresh_solver = jevd.Solver()
+    try:
+        fresh = run_gpu(fresh_solver, wl.G, wl.J, wl.tol, W.MODMODULUS)
+    finally:
+        fresh_solver.close()
+    assert again["st"] == 0 and fresh["st"] == 0
+    assert np.array_equal(again["lam"], fresh["lam"]) and np.array_equal(again["V"], fresh["V"])
