@@ -57,6 +57,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6
+FP32_MFMA_PEAK_TFS = 157.3
 
 
 def pairs_per_sweep(n, ordering):
@@ -638,8 +639,15 @@ def main():
         flops_update = npiv * (2.0 * b) ** 2 * 2.0 * (m + n)
         avg_ms = kms[3] / kl[3]
         achieved = flops_update / (avg_ms * 1e-3) / 1e12
-        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_MFMA_PEAK_TFS,
-                    "unit": "TFLOP/s", "frac": round(achieved / FP64_MFMA_PEAK_TFS, 4),
+        peak = FP64_MFMA_PEAK_TFS
+        if opts.precision:
+            # every sweep has the same launches, so a fraction f32 of them ran
+            # on FP32 MFMA: each launch is held to its own peak, i.e. the peak
+            # is the launch-weighted harmonic mean of the two
+            f32 = sweeps_low / float(sweeps_low + sweeps)
+            peak = 1.0 / (f32 / FP32_MFMA_PEAK_TFS + (1.0 - f32) / FP64_MFMA_PEAK_TFS)
+        roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(peak, 2),
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                     "traffic": (measured_traffic("k_update", args.workload)
                                 if not (opts.precision or opts.pivot) else None),
                     "kernel": "k_update",
@@ -715,8 +723,9 @@ def main():
     if opts.precision:
         out["config"]["sweeps_fp32"] = sweeps_low
         if roofline:
-            roofline["note"] = ("k_update launches of both phases against the FP64 MFMA peak; "
-                                "the FP32 launches run on v_mfma_f32_16x16x4f32 (peak 157.3)")
+            roofline["note"] = ("k_update launches of both phases, each against its own MFMA "
+                                "peak (FP32 157.3, FP64 78.6 TFLOP/s): peak is their "
+                                "launch-weighted harmonic mean")
     if compare:
         out["compare"] = compare
     if kernels:
