@@ -16,10 +16,10 @@
 //                 on the columns of G_P in place instead, still accumulating
 //                 V_P, which is then applied to V only.
 //   k_update      [G_I G_J] <- [G_I G_J] V_P and [V_I V_J] <- [V_I V_J] V_P
-//                 on FP64 MFMA, in place, 64 rows per workgroup: each
-//                 wavefront computes (G_P V_P)^T for 16 rows, so that both the
-//                 loads of G_P and the stores of the result are 16
-//                 consecutive rows per column.
+//                 on FP64 MFMA, in place, four tiles of 64 rows per
+//                 workgroup: each wavefront computes (G_P V_P)^T for 16 rows
+//                 of a tile, so that both the loads of G_P and the stores of
+//                 the result are 16 consecutive rows per column.
 #include <vector>
 
 #include "../../include/jevd.h"
