@@ -30,6 +30,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #if defined(ORC_QUAD)
 #include <quadmath.h>
@@ -481,7 +484,8 @@ static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *
                            int b, int full_block, int sign_pivot, int max_sweeps, int max_inner,
                            int accumulate_v, double *lambda, double *V, int ldv,
                            int *sweeps_out, long long *rot_per_sweep,
-                           long long *nbreakdown_out, int max_steps, signed char *J_out);
+                           long long *nbreakdown_out, int max_steps, signed char *J_out,
+                           int nthreads);
 
 int SFX(orc_block_jevd)(int m, int n, double *G, int ldg, const signed char *J, double tol,
                         int b, int full_block, int max_sweeps, int max_inner,
@@ -491,7 +495,7 @@ int SFX(orc_block_jevd)(int m, int n, double *G, int ldg, const signed char *J, 
 {
     return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, 0, max_sweeps, max_inner,
                            accumulate_v, lambda, V, ldv, sweeps_out, rot_per_sweep,
-                           nbreakdown_out, -1, NULL);
+                           nbreakdown_out, -1, NULL, 1);
 }
 
 /* The same with the sign-pivoted Cholesky of Alg. 3.3 (HBSC / HFSC; for
@@ -506,58 +510,266 @@ int SFX(orc_block_jevd_sp)(int m, int n, double *G, int ldg, const signed char *
 {
     return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, 1, max_sweeps, max_inner,
                            accumulate_v, lambda, V, ldv, sweeps_out, rot_per_sweep,
-                           nbreakdown_out, -1, J_out);
+                           nbreakdown_out, -1, J_out, 1);
 }
 
 /* The first max_steps outer steps of the first sweep only: a bounded sample
  * of the block algorithm's work, used to time the oracle on inputs too large
- * to solve on the CPU.  Returns the status of the partial run. */
+ * to solve on the CPU.  G receives the iterate after those steps.  Returns
+ * the status of the partial run.  nthreads as for orc_block_jevd_mt. */
 int SFX(orc_block_steps)(int m, int n, double *G, int ldg, const signed char *J, double tol,
-                         int b, int full_block, int max_inner, int max_steps, int sign_pivot)
+                         int b, int full_block, int max_inner, int max_steps, int sign_pivot,
+                         int nthreads)
 {
     int sweeps = 0;
     return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, sign_pivot, 1, max_inner, 0, NULL,
-                           NULL, n, &sweeps, NULL, NULL, max_steps, NULL);
+                           NULL, n, &sweeps, NULL, NULL, max_steps, NULL, nthreads);
+}
+
+/* orc_block_jevd / orc_block_jevd_sp with the pivots of each outer step
+ * spread over nthreads threads (<= 0: all).  The pivots of a step touch
+ * disjoint columns of G and V (Sec. 3: the processes of a step work on
+ * disjoint block pairs), and each pivot runs the same operations in the same
+ * order as in the sequential routine, so on finite data the results are bit
+ * for bit those of orc_block_jevd (a non-finite Gram may stop a different
+ * set of pivots in that step; the status is the same). */
+int SFX(orc_block_jevd_mt)(int m, int n, double *G, int ldg, const signed char *J, double tol,
+                           int b, int full_block, int sign_pivot, int max_sweeps, int max_inner,
+                           int accumulate_v, double *lambda, double *V, int ldv,
+                           int *sweeps_out, long long *rot_per_sweep,
+                           long long *nbreakdown_out, signed char *J_out, int nthreads)
+{
+    return block_jevd_impl(m, n, G, ldg, J, tol, b, full_block, sign_pivot, max_sweeps, max_inner,
+                           accumulate_v, lambda, V, ldv, sweeps_out, rot_per_sweep,
+                           nbreakdown_out, -1, J_out, nthreads);
+}
+
+/* Work arrays of one pivot (one set per thread). */
+typedef struct {
+    real *GP, *VB, *AP, *R, *VP, *SW, *VQ;
+    signed char *JP, *JS;
+    int *colp, *perm, *iw, *istart, *ipairs;
+} pivot_work;
+
+static void pivot_work_free(pivot_work *w)
+{
+    free(w->GP); free(w->VB); free(w->AP); free(w->R); free(w->VP); free(w->SW); free(w->VQ);
+    free(w->JP); free(w->JS); free(w->colp); free(w->perm); free(w->iw); free(w->istart);
+    free(w->ipairs);
+    memset(w, 0, sizeof(*w));
+}
+
+static int pivot_work_alloc(pivot_work *w, int m, int n, int wmax)
+{
+    int maxp = wmax * wmax;                   /* bound on inner pair counts */
+    memset(w, 0, sizeof(*w));
+    w->GP = (real *)malloc(sizeof(real) * (size_t)m * wmax);
+    w->VB = (real *)malloc(sizeof(real) * (size_t)n * wmax);
+    w->AP = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
+    w->R = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
+    w->VP = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
+    w->SW = (real *)malloc(sizeof(real) * 3 * (size_t)wmax * wmax);
+    w->VQ = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
+    w->JP = (signed char *)malloc((size_t)wmax);
+    w->JS = (signed char *)malloc((size_t)wmax);
+    w->colp = (int *)malloc(sizeof(int) * (size_t)wmax);
+    w->perm = (int *)malloc(sizeof(int) * (size_t)wmax);
+    w->iw = (int *)malloc(sizeof(int) * 3 * (size_t)wmax);
+    w->istart = (int *)malloc(sizeof(int) * (size_t)(wmax + 1));
+    w->ipairs = (int *)malloc(sizeof(int) * 2 * (size_t)maxp);
+    if (!w->GP || !w->VB || !w->AP || !w->R || !w->VP || !w->SW || !w->VQ || !w->JP || !w->JS ||
+        !w->colp || !w->perm || !w->iw || !w->istart || !w->ipairs) {
+        pivot_work_free(w);
+        return ORC_ENOMEM;
+    }
+    return ORC_OK;
+}
+
+/* Steps 1-5 above on the pivot block (I, J) = (blocks bi, bj) of the iterate
+ * Gr (m x n, ld m) and Vr (n x n, ld n, may be NULL); Jc holds the current
+ * column signs.  all_pairs: the inner sweep covers all pairs (full block, or
+ * the first step of a block-oriented sweep).  Adds the pivot's rotations,
+ * clamps and breakdowns to the counters; sets *bad on a non-finite Gram
+ * (then G and V are left as they were for this pivot). */
+static void block_pivot(int m, int n, real *Gr, real *Vr, signed char *Jc, const int *bstart,
+                        int bi, int bj, int all_pairs, int full_block, int sign_pivot,
+                        int max_inner, real tol, pivot_work *pw, long long *rot,
+                        long long *nclamp, long long *nbreak, int *bad)
+{
+    real *GP = pw->GP, *VB = pw->VB, *AP = pw->AP, *R = pw->R, *VP = pw->VP, *VQ = pw->VQ;
+    signed char *JP = pw->JP, *JS = pw->JS;
+    int *colp = pw->colp, *perm = pw->perm;
+    int wi = bstart[bi + 1] - bstart[bi], wj = bstart[bj + 1] - bstart[bj];
+    int w = wi + wj;
+    for (int k = 0; k < wi; ++k) colp[k] = bstart[bi] + k;
+    for (int k = 0; k < wj; ++k) colp[wi + k] = bstart[bj] + k;
+    for (int k = 0; k < w; ++k) {
+        JP[k] = Jc[colp[k]];
+        memcpy(GP + (size_t)k * m, Gr + (size_t)colp[k] * m, sizeof(real) * (size_t)m);
+    }
+    /* 1. pivot Gram, each entry summed over the rows in order; a_kl and a_lk
+     * are the same sum of the same products (x y = y x), so each is formed
+     * once and mirrored; up to four entries of a row of A_P are summed side
+     * by side (independent sums, each in its own order) */
+    for (int k = 0; k < w; ++k)
+        for (int l0 = k; l0 < w; l0 += 4) {
+            const int nl = (w - l0 < 4) ? w - l0 : 4;
+            const real *x = GP + (size_t)k * m;
+            const real *y0 = GP + (size_t)l0 * m;
+            real acc[4] = {0, 0, 0, 0};
+            if (nl == 4) {
+                for (int r = 0; r < m; ++r) {
+                    acc[0] = acc[0] + x[r] * y0[r];
+                    acc[1] = acc[1] + x[r] * y0[(size_t)m + r];
+                    acc[2] = acc[2] + x[r] * y0[2 * (size_t)m + r];
+                    acc[3] = acc[3] + x[r] * y0[3 * (size_t)m + r];
+                }
+            } else {
+                for (int q = 0; q < nl; ++q)
+                    for (int r = 0; r < m; ++r) acc[q] = acc[q] + x[r] * y0[(size_t)q * m + r];
+            }
+            for (int q = 0; q < nl; ++q) {
+                AP[(size_t)(l0 + q) * w + k] = acc[q];
+                AP[(size_t)k * w + l0 + q] = acc[q];
+            }
+        }
+    /* 2. skip test on the targeted entries */
+    int need = 0;
+    for (int k = 0; k < w; ++k)
+        for (int l = k + 1; l < w; ++l) {
+            if (!all_pairs && !(k < wi && l >= wi)) continue;
+            real akk = AP[(size_t)k * w + k], all = AP[(size_t)l * w + l];
+            real akl = AP[(size_t)l * w + k];
+            if (!is_finite_r(akk) || !is_finite_r(all) || !is_finite_r(akl)) {
+                *bad = 1;
+                return;
+            }
+            if (akk != 0 && all != 0 && R_FABS(akl) > tol * R_SQRT(akk) * R_SQRT(all))
+                need = 1;
+        }
+    if (!need) return;
+    /* 3. Cholesky A_P = R^T R (upper R, column-major w x w); with sign
+     * pivoting P^T A_P P = R_S^T R_S (Alg. 3.3) and the inner signs become
+     * those of the permuted positions */
+    int broke = 0, npos = 0;
+    for (int k = 0; k < w; ++k) { perm[k] = k; JS[k] = JP[k]; }
+    if (sign_pivot) {
+        broke = sign_pivoted_cholesky(w, AP, JP, R, perm, &npos, pw->SW, pw->iw);
+        if (broke) {
+            for (int k = 0; k < w; ++k) perm[k] = k;
+        } else {
+            for (int k = 0; k < w; ++k) JS[k] = (k < npos) ? 1 : -1;
+        }
+    }
+    for (int j = 0; j < w && !broke && !sign_pivot; ++j) {
+        for (int i = 0; i <= j; ++i) {
+            real sum = AP[(size_t)j * w + i];
+            for (int k = 0; k < i; ++k)
+                sum = sum - R[(size_t)i * w + k] * R[(size_t)j * w + k];
+            if (i == j) {
+                if (!(sum > 0)) { broke = 1; break; }
+                R[(size_t)j * w + j] = R_SQRT(sum);
+            } else {
+                R[(size_t)j * w + i] = sum / R[(size_t)i * w + i];
+            }
+        }
+        for (int i = j + 1; i < w; ++i) R[(size_t)j * w + i] = 0;
+    }
+    if (broke) ++*nbreak;
+    /* 4. inner one-sided Jacobi on R (or on G_P after a breakdown) */
+    real *X = broke ? GP : R;
+    int ldx = broke ? m : w, len = broke ? m : w;
+    for (int k = 0; k < w; ++k)
+        for (int l = 0; l < w; ++l) VP[(size_t)k * w + l] = (real)(k == l ? 1 : 0);
+    long long prot = 0;
+    int isteps, inp = 0;
+    if (all_pairs) {
+        isteps = orc_ordering(w, 2, pw->istart, pw->ipairs, &inp);
+    } else {
+        isteps = cross_ordering(wi, wj, pw->istart, pw->ipairs);
+    }
+    int inner = full_block ? max_inner : 1;
+    for (int it = 0; it < inner; ++it) {
+        long long r = inner_sweep(X, ldx, len, VP, w, pw->istart, pw->ipairs, isteps,
+                                  broke ? JP : JS, tol, nclamp, bad);
+        prot += r;
+        if (*bad || r == 0) break;
+    }
+    if (*bad) return;
+    *rot += prot;
+    if (prot == 0) return;
+    /* 5. update G_P <- G_P V_P, V(:,P) <- V(:,P) V_P.  After a breakdown
+     * G_P was transformed in place and is copied back.  With sign pivoting
+     * V_P = P V': the permutation is applied to the rows of the accumulated
+     * V' (Alg. 3.4), and column c of the block takes the sign of position c.
+     * Each entry of a product is the sum over k = 0..w-1 in that order; the
+     * loops run over the rows innermost (the sums themselves are unchanged). */
+    if (sign_pivot && !broke) {
+        memcpy(VQ, VP, sizeof(real) * (size_t)w * w);
+        for (int c = 0; c < w; ++c)
+            for (int r = 0; r < w; ++r) VP[(size_t)c * w + perm[r]] = VQ[(size_t)c * w + r];
+        for (int c = 0; c < w; ++c) Jc[colp[c]] = JS[c];
+    }
+    if (broke) {
+        for (int c = 0; c < w; ++c)
+            memcpy(Gr + (size_t)colp[c] * m, GP + (size_t)c * m, sizeof(real) * (size_t)m);
+    } else {
+        for (int c = 0; c < w; ++c) {
+            real *out = Gr + (size_t)colp[c] * m;
+            for (int r = 0; r < m; ++r) out[r] = 0;
+            for (int k = 0; k < w; ++k) {
+                const real v = VP[(size_t)c * w + k], *in = GP + (size_t)k * m;
+                for (int r = 0; r < m; ++r) out[r] = out[r] + in[r] * v;
+            }
+        }
+    }
+    if (Vr) {
+        for (int k = 0; k < w; ++k)
+            memcpy(VB + (size_t)k * n, Vr + (size_t)colp[k] * n, sizeof(real) * (size_t)n);
+        for (int c = 0; c < w; ++c) {
+            real *out = Vr + (size_t)colp[c] * n;
+            for (int r = 0; r < n; ++r) out[r] = 0;
+            for (int k = 0; k < w; ++k) {
+                const real v = VP[(size_t)c * w + k], *in = VB + (size_t)k * n;
+                for (int r = 0; r < n; ++r) out[r] = out[r] + in[r] * v;
+            }
+        }
+    }
 }
 
 static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *J, double tol,
                            int b, int full_block, int sign_pivot, int max_sweeps, int max_inner,
                            int accumulate_v, double *lambda, double *V, int ldv,
                            int *sweeps_out, long long *rot_per_sweep,
-                           long long *nbreakdown_out, int max_steps, signed char *J_out)
+                           long long *nbreakdown_out, int max_steps, signed char *J_out,
+                           int nthreads)
 {
     int st = check_args(m, n, ldg, J, ldv, V);
     if (st) return st;
     if (b < 1 || max_sweeps < 1 || max_inner < 1) return ORC_EINVAL;
     int N = 2 * ((n + 2 * b - 1) / (2 * b));
     if (N > n) return ORC_EINVAL;             /* every block needs a column */
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_num_procs();
+#else
+    nthreads = 1;
+#endif
+    if (nthreads > N / 2) nthreads = N / 2;   /* pivots per step */
+    if (nthreads < 1) nthreads = 1;
     int *bstart = (int *)malloc(sizeof(int) * (size_t)(N + 1));
     int onp = 0;
     int ons = orc_ordering(N, 2, NULL, NULL, &onp);
     int *ostart = (int *)malloc(sizeof(int) * (size_t)(ons + 1));
     int *opairs = (int *)malloc(sizeof(int) * 2 * (size_t)onp);
     int wmax = 2 * (n / N + 1);
-    int maxp = wmax * wmax;                   /* bound on inner pair counts */
-    int *istart = (int *)malloc(sizeof(int) * (size_t)(wmax + 1));
-    int *ipairs = (int *)malloc(sizeof(int) * 2 * (size_t)maxp);
     real *Gr = (real *)malloc(sizeof(real) * (size_t)m * n);
     real *Vr = V ? (real *)malloc(sizeof(real) * (size_t)n * n) : NULL;
-    real *GP = (real *)malloc(sizeof(real) * (size_t)m * wmax);
-    real *VB = (real *)malloc(sizeof(real) * (size_t)n * wmax);
-    real *AP = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
-    real *R = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
-    real *VP = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
-    signed char *JP = (signed char *)malloc((size_t)wmax);
-    signed char *JS = (signed char *)malloc((size_t)wmax);
     signed char *Jc = (signed char *)malloc((size_t)n);
-    int *colp = (int *)malloc(sizeof(int) * (size_t)wmax);
-    int *perm = (int *)malloc(sizeof(int) * (size_t)wmax);
-    int *iw = (int *)malloc(sizeof(int) * 3 * (size_t)wmax);
-    real *SW = (real *)malloc(sizeof(real) * 3 * (size_t)wmax * wmax);
-    real *VQ = (real *)malloc(sizeof(real) * (size_t)wmax * wmax);
-    if (!bstart || !ostart || !opairs || !istart || !ipairs || !Gr || (V && !Vr) ||
-        !GP || !VB || !AP || !R || !VP || !JP || !JS || !Jc || !colp || !perm || !iw || !SW ||
-        !VQ) {
+    pivot_work *pw = (pivot_work *)calloc((size_t)nthreads, sizeof(pivot_work));
+    int ok = bstart && ostart && opairs && Gr && (!V || Vr) && Jc && pw;
+    for (int t = 0; ok && t < nthreads; ++t)
+        if (pivot_work_alloc(&pw[t], m, n, wmax)) ok = 0;
+    if (!ok) {
         st = ORC_ENOMEM;
         goto out;
     }
@@ -580,127 +792,22 @@ static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *
         int bad = 0;
         ++sweeps;
         for (int sidx = 0; sidx < ons && !bad && (max_steps < 0 || sidx < max_steps); ++sidx) {
-            for (int e = ostart[sidx]; e < ostart[sidx + 1] && !bad; ++e) {
-                int I = opairs[2 * e], Jb = opairs[2 * e + 1];
-                int wi = bstart[I + 1] - bstart[I], wj = bstart[Jb + 1] - bstart[Jb];
-                int w = wi + wj;
-                for (int k = 0; k < wi; ++k) colp[k] = bstart[I] + k;
-                for (int k = 0; k < wj; ++k) colp[wi + k] = bstart[Jb] + k;
-                for (int k = 0; k < w; ++k) {
-                    JP[k] = Jc[colp[k]];
-                    memcpy(GP + (size_t)k * m, Gr + (size_t)colp[k] * m, sizeof(real) * (size_t)m);
-                }
-                /* 1. pivot Gram */
-                for (int k = 0; k < w; ++k)
-                    for (int l = 0; l < w; ++l) {
-                        real acc = 0;
-                        for (int r = 0; r < m; ++r)
-                            acc = acc + GP[(size_t)k * m + r] * GP[(size_t)l * m + r];
-                        AP[(size_t)l * w + k] = acc;
-                    }
-                /* 2. skip test on the targeted entries */
-                int all_pairs = full_block || sidx == 0;
-                int need = 0;
-                for (int k = 0; k < w && !bad; ++k)
-                    for (int l = k + 1; l < w; ++l) {
-                        if (!all_pairs && !(k < wi && l >= wi)) continue;
-                        real akk = AP[(size_t)k * w + k], all = AP[(size_t)l * w + l];
-                        real akl = AP[(size_t)l * w + k];
-                        if (!is_finite_r(akk) || !is_finite_r(all) || !is_finite_r(akl)) {
-                            bad = 1; break;
-                        }
-                        if (akk != 0 && all != 0 &&
-                            R_FABS(akl) > (real)tol * R_SQRT(akk) * R_SQRT(all))
-                            need = 1;
-                    }
-                if (bad || !need) continue;
-                /* 3. Cholesky A_P = R^T R (upper R, column-major w x w); with
-                 * sign pivoting P^T A_P P = R_S^T R_S (Alg. 3.3) and the inner
-                 * signs become those of the permuted positions */
-                int broke = 0, npos = 0;
-                for (int k = 0; k < w; ++k) { perm[k] = k; JS[k] = JP[k]; }
-                if (sign_pivot) {
-                    broke = sign_pivoted_cholesky(w, AP, JP, R, perm, &npos, SW, iw);
-                    if (broke) {
-                        for (int k = 0; k < w; ++k) perm[k] = k;
-                    } else {
-                        for (int k = 0; k < w; ++k) JS[k] = (k < npos) ? 1 : -1;
-                    }
-                }
-                for (int j = 0; j < w && !broke && !sign_pivot; ++j) {
-                    for (int i = 0; i <= j; ++i) {
-                        real sum = AP[(size_t)j * w + i];
-                        for (int k = 0; k < i; ++k)
-                            sum = sum - R[(size_t)i * w + k] * R[(size_t)j * w + k];
-                        if (i == j) {
-                            if (!(sum > 0)) { broke = 1; break; }
-                            R[(size_t)j * w + j] = R_SQRT(sum);
-                        } else {
-                            R[(size_t)j * w + i] = sum / R[(size_t)i * w + i];
-                        }
-                    }
-                    for (int i = j + 1; i < w; ++i) R[(size_t)j * w + i] = 0;
-                }
-                if (broke) ++nbreak;
-                /* 4. inner one-sided Jacobi on R (or on G_P after a breakdown) */
-                real *X = broke ? GP : R;
-                int ldx = broke ? m : w, len = broke ? m : w;
-                for (int k = 0; k < w; ++k)
-                    for (int l = 0; l < w; ++l) VP[(size_t)k * w + l] = (real)(k == l ? 1 : 0);
-                long long prot = 0;
-                int isteps, inp = 0;
-                if (all_pairs) {
-                    isteps = orc_ordering(w, 2, istart, ipairs, &inp);
-                } else {
-                    isteps = cross_ordering(wi, wj, istart, ipairs);
-                }
-                int inner = full_block ? max_inner : 1;
-                for (int it = 0; it < inner; ++it) {
-                    long long r = inner_sweep(X, ldx, len, VP, w, istart, ipairs, isteps,
-                                              broke ? JP : JS, (real)tol, &nclamp, &bad);
-                    prot += r;
-                    if (bad || r == 0) break;
-                }
-                if (bad) break;
-                rot += prot;
-                /* 5. update G_P <- G_P V_P, V(:,P) <- V(:,P) V_P.  After a
-                 * breakdown G_P was transformed in place and is copied back.
-                 * With sign pivoting V_P = P V': the permutation is applied
-                 * to the rows of the accumulated V' (Alg. 3.4), and column c
-                 * of the block takes the sign of position c. */
-                if (prot > 0 && sign_pivot && !broke) {
-                    memcpy(VQ, VP, sizeof(real) * (size_t)w * w);
-                    for (int c = 0; c < w; ++c)
-                        for (int r = 0; r < w; ++r) VP[(size_t)c * w + perm[r]] = VQ[(size_t)c * w + r];
-                    for (int c = 0; c < w; ++c) Jc[colp[c]] = JS[c];
-                }
-                if (prot > 0) {
-                    if (broke) {
-                        for (int c = 0; c < w; ++c)
-                            memcpy(Gr + (size_t)colp[c] * m, GP + (size_t)c * m,
-                                   sizeof(real) * (size_t)m);
-                    } else {
-                        for (int c = 0; c < w; ++c)
-                            for (int r = 0; r < m; ++r) {
-                                real acc = 0;
-                                for (int k = 0; k < w; ++k)
-                                    acc = acc + GP[(size_t)k * m + r] * VP[(size_t)c * w + k];
-                                Gr[(size_t)colp[c] * m + r] = acc;
-                            }
-                    }
-                    if (Vr) {
-                        for (int k = 0; k < w; ++k)
-                            memcpy(VB + (size_t)k * n, Vr + (size_t)colp[k] * n,
-                                   sizeof(real) * (size_t)n);
-                        for (int c = 0; c < w; ++c)
-                            for (int r = 0; r < n; ++r) {
-                                real acc = 0;
-                                for (int k = 0; k < w; ++k)
-                                    acc = acc + VB[(size_t)k * n + r] * VP[(size_t)c * w + k];
-                                Vr[(size_t)colp[c] * n + r] = acc;
-                            }
-                    }
-                }
+            const int e0 = ostart[sidx], e1 = ostart[sidx + 1];
+            const int all_pairs = full_block || sidx == 0;
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nthreads) schedule(static, 1) \
+    reduction(+ : rot, nclamp, nbreak) reduction(| : bad)
+#endif
+            for (int e = e0; e < e1; ++e) {
+                int t = 0;
+#ifdef _OPENMP
+                t = omp_get_thread_num();
+#endif
+                /* in a sequential run a non-finite Gram ends the step at once */
+                if (nthreads == 1 && bad) continue;
+                block_pivot(m, n, Gr, Vr, Jc, bstart, opairs[2 * e], opairs[2 * e + 1],
+                            all_pairs, full_block, sign_pivot, max_inner, (real)tol, &pw[t],
+                            &rot, &nclamp, &nbreak, &bad);
             }
         }
         if (rot_per_sweep) rot_per_sweep[sweeps - 1] = rot;
@@ -715,8 +822,7 @@ static int block_jevd_impl(int m, int n, double *G, int ldg, const signed char *
     if (sweeps_out) *sweeps_out = sweeps;
     if (nbreakdown_out) *nbreakdown_out = nbreak;
 out:
-    free(bstart); free(ostart); free(opairs); free(istart); free(ipairs);
-    free(Gr); free(Vr); free(GP); free(VB); free(AP); free(R); free(VP); free(JP);
-    free(JS); free(Jc); free(colp); free(perm); free(iw); free(SW); free(VQ);
+    for (int t = 0; pw && t < nthreads; ++t) pivot_work_free(&pw[t]);
+    free(pw); free(bstart); free(ostart); free(opairs); free(Gr); free(Vr); free(Jc);
     return st;
 }

@@ -64,7 +64,14 @@ def lib():
             f.restype = ctypes.c_int
             f = getattr(L, "orc_block_steps_" + s)
             f.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _cp, ctypes.c_double,
-                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+                          ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int]
+            f.restype = ctypes.c_int
+            f = getattr(L, "orc_block_jevd_mt_" + s)
+            f.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _cp,
+                          ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int, _ip,
+                          _llp, _llp, _cp, ctypes.c_int]
             f.restype = ctypes.c_int
             f = getattr(L, "orc_rotation_" + s)
             f.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -146,10 +153,13 @@ def jevd(G, J=None, tol=None, ordering_kind=MODMODULUS, max_sweeps=50, want_v=Tr
 
 
 def block_jevd(G, J=None, tol=None, b=8, full_block=False, max_sweeps=50, max_inner=30,
-               want_v=True, V0=None, prec="d", sign_pivot=False):
+               want_v=True, V0=None, prec="d", sign_pivot=False, nthreads=1):
     """Block one-sided Jacobi; see oracle/jacobi.c.  sign_pivot selects the
     sign-pivoted Cholesky of Alg. 3.3 (HBSC / HFSC); the result's .J then
-    holds the final column signs (the pivoting permutes them)."""
+    holds the final column signs (the pivoting permutes them).  nthreads > 1
+    (or <= 0: all cores) spreads the disjoint pivots of each step over
+    threads (orc_block_jevd_mt), with results bit for bit those of the
+    sequential run."""
     G, m, n, Jb, V = _prep(G, J, want_v, V0)
     if tol is None:
         tol = n * np.finfo(np.float64).eps
@@ -162,7 +172,12 @@ def block_jevd(G, J=None, tol=None, b=8, full_block=False, max_sweeps=50, max_in
             1 if V0 is not None else 0, _ptr(lam), None if V is None else _ptr(V), n,
             ctypes.byref(sweeps), _ptr(rot, _llp), ctypes.byref(nbr)]
     Jout = np.ones(n, dtype=np.int8)
-    if sign_pivot:
+    if nthreads != 1:
+        st = getattr(lib(), "orc_block_jevd_mt_" + prec)(
+            *args[:8], 1 if sign_pivot else 0, *args[8:], Jout.ctypes.data_as(_cp), int(nthreads))
+        if not sign_pivot and Jb is not None:
+            Jout = Jb.copy()
+    elif sign_pivot:
         st = getattr(lib(), "orc_block_jevd_sp_" + prec)(*args, Jout.ctypes.data_as(_cp))
     else:
         st = getattr(lib(), "orc_block_jevd_" + prec)(*args)
@@ -188,15 +203,16 @@ def sp_cholesky(A, JP, prec="d"):
 
 
 def block_steps(G, J=None, tol=None, b=32, full_block=False, max_inner=30, steps=1, prec="d",
-                sign_pivot=False):
+                sign_pivot=False, nthreads=1):
     """The first `steps` outer steps of one block sweep (a bounded sample of
-    the block algorithm's work); returns (status, G after those steps)."""
+    the block algorithm's work); returns (status, G after those steps).
+    nthreads as for block_jevd."""
     G, m, n, Jb, _ = _prep(G, J, False, None)
     if tol is None:
         tol = n * np.finfo(np.float64).eps
     f = getattr(lib(), "orc_block_steps_" + prec)
     st = f(m, n, _ptr(G), m, None if Jb is None else Jb.ctypes.data_as(_cp), float(tol), b,
-           1 if full_block else 0, max_inner, steps, 1 if sign_pivot else 0)
+           1 if full_block else 0, max_inner, steps, 1 if sign_pivot else 0, int(nthreads))
     return st, G
 
 

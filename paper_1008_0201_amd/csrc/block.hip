@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     double *red = VP + W * P;          // NW x 3 x NP partial dot products
     __shared__ signed char JP[W], JS[W];
     __shared__ int s_piv[W], s_perm[W];
-    __shared__ int s_need, s_bad, s_broke, s_npos;
+    __shared__ int s_need, s_bad, s_npos;
     __shared__ unsigned long long s_rot[NW], s_cl[NW];
     const int pv = blockIdx.x;
     const int2 IJ = a.piv[pv];
@@ -370,7 +370,6 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     if (tid == 0) {
         s_need = 0;
         s_bad = 0;
-        s_broke = 0;
     }
     // A_P: the split partials (upper tiles) added in split order, mirrored
     // to the lower part; 8 splits of 4 entries are loaded at a time
@@ -435,11 +434,15 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     // Cholesky A_P = R^T R, right-looking: step j writes row j of R
     // (r_jl = a_jl / r_jj) into the VP buffer, then, after a barrier,
     // subtracts r_ji r_jl from the trailing entries (i, l), j < i <= l.
+    // A breakdown is seen by every thread at once: the pivot d is read from
+    // LDS after a barrier, so each thread records it in its own register and
+    // all leave the loop at the same step.
+    bool broke = false;
     if (!a.sign_pivot) {
         for (int j = 0; j < W; ++j) {
             const double d = A[j * P + j];
             if (!(d > 0.0)) {
-                if (tid == 0) s_broke = 1;
+                broke = true;
                 break;  // d is the same for every thread: a uniform exit
             }
             const double rjj = sqrt(d);
@@ -512,7 +515,7 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
             const int pj = s_piv[j];
             const double d = A[pj * P + pj];
             if (!(d > 0.0)) {
-                if (tid == 0) s_broke = 1;
+                broke = true;
                 break;  // uniform exit
             }
             const double rjj = sqrt(d);
@@ -528,7 +531,6 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
             __syncthreads();
         }
     }
-    const bool broke = s_broke != 0;
     if (broke && !a.G) {
         // no FP64 copy of G to transform in place (the FP32 sweeps): the
         // pivot is left to the FP64 sweeps that follow

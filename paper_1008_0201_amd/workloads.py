@@ -80,18 +80,58 @@ def graded_hyperbolic(n=1024, k=1, m=None, grade=3.0, ordering=MODMODULUS):
     return Workload("hyperbolic-graded-n%d" % n, G, J, n * DBL_EPS, ordering)
 
 
-def graded_spd_known_factor(n=8192, k=2, lam_decades=6.0, row_decades=4.0,
-                            ordering=MODMODULUS):
-    """Positive definite, row-graded: G = D Q diag(lam) Q^T with Q Haar,
-    lam_k = 10^U(-lam_decades, 0) and D = diag(10^U(-row_decades, row_decades));
-    J = I, tol = n eps.  At n = 8192 this is the block-sweep workload."""
+# The QR and the product of the row-graded recipe below run in OpenBLAS, whose
+# results depend on the CPU kernel it picks and on its thread count.  So that
+# every machine produces the same bytes (eigenvalues of an input can then be
+# computed once, on any machine, and looked up by the input's SHA-256), that
+# recipe runs in a child process with both fixed: the AVX2 (Haswell) kernels,
+# which every x86-64 host here has, and 8 threads.
+FIXED_BLAS_ENV = {"OPENBLAS_CORETYPE": "Haswell", "OPENBLAS_NUM_THREADS": "8",
+                  "OMP_NUM_THREADS": "8"}
+
+
+def _graded_spd_factor_here(n, k, lam_decades, row_decades):
     g = rng(k)
     Q = haar_orthogonal(n, g)
     lam = 10.0 ** g.uniform(-lam_decades, 0.0, size=n)
     d = 10.0 ** g.uniform(-row_decades, row_decades, size=n)
     A = (Q * lam[None, :]) @ Q.T
-    G = d[:, None] * A
+    return d[:, None] * A
+
+
+def _graded_spd_factor_fixed_blas(n, k, lam_decades, row_decades):
+    """_graded_spd_factor_here in a child process with FIXED_BLAS_ENV."""
+    import os
+    import subprocess
+    import sys
+    import tempfile
+    here = os.path.dirname(os.path.abspath(__file__))
+    env = dict(os.environ)
+    env.update(FIXED_BLAS_ENV)
+    with tempfile.TemporaryDirectory() as td:
+        out = os.path.join(td, "G.npy")
+        code = ("import sys, numpy as np; sys.path.insert(0, %r); "
+                "from paper_1008_0201_amd import workloads as W; "
+                "np.save(%r, W._graded_spd_factor_here(%d, %d, %r, %r))"
+                % (os.path.dirname(here), out, n, k, float(lam_decades), float(row_decades)))
+        subprocess.run([sys.executable, "-c", code], env=env, check=True)
+        return np.load(out)
+
+
+def graded_spd_known_factor(n=8192, k=2, lam_decades=6.0, row_decades=4.0,
+                            ordering=MODMODULUS):
+    """Positive definite, row-graded: G = D Q diag(lam) Q^T with Q Haar,
+    lam_k = 10^U(-lam_decades, 0) and D = diag(10^U(-row_decades, row_decades));
+    J = I, tol = n eps.  At n = 8192 this is the block-sweep workload.  The
+    same bytes on every machine (FIXED_BLAS_ENV)."""
+    G = _graded_spd_factor_fixed_blas(n, k, lam_decades, row_decades)
     return Workload("spd-rowgraded-n%d" % n, G, None, n * DBL_EPS, ordering)
+
+
+def input_sha256(G):
+    """SHA-256 (hex) of a factor's bytes in column-major order."""
+    import hashlib
+    return hashlib.sha256(np.asfortranarray(G, dtype=np.float64).tobytes(order="F")).hexdigest()
 
 
 def graded_spd_transposed(n=8192, k=2, lam_decades=3.0, row_decades=4.0):

@@ -1,8 +1,8 @@
 """GPU parity of the sign-pivoted block variants (Alg. 3.3 in the pivot
 solve: HBSC / HFSC; diagonal pivoting for J = I) against the oracle's
 sign-pivoted block solve on the same seeded inputs: eigenvalues as for the
-unpivoted block path (1e-12, or within 4x of the FP64 oracle's own error
-against binary128), sweep counts within one, the inertia of J kept,
+unpivoted block path (1e-12, or the bound (1.2) against a high-precision
+oracle run: oracle/gates.py), sweep counts within one, the inertia of J kept,
 V^T J V = diag(sign(lambda)) and G_out = G_in V.  Needs an MI355X."""
 import numpy as np
 import pytest
@@ -83,3 +83,28 @@ def test_sign_pivot_option_rules(solver):
     assert st == jevd.JEVD_EINVAL          # pointwise has no Cholesky
     lam, U, V, sweeps, st = solver.evd(G, None, variant=1, block=16, check=False, pivot=2)
     assert st == jevd.JEVD_EINVAL
+
+
+@pytest.mark.parametrize("full_block", [False, True])
+def test_sign_pivoted_breakdown(solver, orc, full_block):
+    """A zero column breaks the sign-pivoted Cholesky of its pivots down
+    (Alg. 3.3 meets a zero pivot): on both sides such a pivot is processed
+    on the columns of G_P with the unpivoted signs (no column moves), and the
+    result meets the gates of the other sign-pivoted cases."""
+    n = 128
+    wl = W.graded_hyperbolic(n, k=433, grade=2.0)
+    G = wl.G.copy()
+    G[:, 45] = 0.0
+    got = run_sp(solver, G, wl.J, wl.tol, full_block, 16)
+    info = solver.info()
+    ref = orc.block_jevd(G, wl.J, wl.tol, b=16, full_block=full_block, sign_pivot=True)
+    assert ref.extra > 0 and info.breakdowns > 0
+    assert ref.status == 0 and got["st"] == 0
+    zero = np.flatnonzero(got["lam"] == 0.0)
+    assert len(zero) == 1 and np.all(got["U"][:, zero[0]] == 0.0)
+    nz = got["lam"] != 0.0
+    nzr = ref.lam != 0.0
+    Gs = np.delete(G, 45, axis=1)
+    Js = np.delete(wl.J, 45)
+    check_eigs(orc, Gs, Js, got["lam"][nz], ref.lam[nzr])
+    assert abs(got["sweeps"] - ref.sweeps) <= 1, (got["sweeps"], ref.sweeps)

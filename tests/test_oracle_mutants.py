@@ -36,8 +36,13 @@ MUTANTS = {
     "modmod-extra-pair-wrong": ("ordering.c", "int i = k / 2, j = k / 2 + n / 2;",
                                 "int i = k / 2, j = k / 2 + n / 2 - 1;"),
     "block-update-transposed": ("jacobi.c",
-                                "acc = acc + GP[(size_t)k * m + r] * VP[(size_t)c * w + k];",
-                                "acc = acc + GP[(size_t)k * m + r] * VP[(size_t)k * w + c];"),
+                                "const real v = VP[(size_t)c * w + k], *in = GP + (size_t)k * m;",
+                                "const real v = VP[(size_t)k * w + c], *in = GP + (size_t)k * m;"),
+    "block-gram-wrong-column": ("jacobi.c",
+                                "acc[2] = acc[2] + x[r] * y0[2 * (size_t)m + r];",
+                                "acc[2] = acc[2] + x[r] * y0[(size_t)m + r];"),
+    "block-gram-not-mirrored": ("jacobi.c", "                AP[(size_t)k * w + l0 + q] = acc[q];\n",
+                                ""),
     "sp-reversal-dropped": ("jacobi.c", "const int src = pp[nn - 1 - c];", "const int src = pp[c];"),
     "sp-pivot-smallest": ("jacobi.c", "if (W[(size_t)i * k + i] > W[(size_t)t * k + t]) t = i;",
                           "if (W[(size_t)i * k + i] < W[(size_t)t * k + t]) t = i;"),

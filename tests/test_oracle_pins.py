@@ -501,3 +501,52 @@ def test_block_single_pivot_is_whole_matrix(orc):
     assert res.sweeps <= 3
     truth = _eig_mpmath(G, None, dps=60)
     assert _rel(res.lam, truth) <= 1e-13
+
+
+# ------------------------------------- threaded block oracle and step sample
+@pytest.mark.parametrize("n,b,full_block,sign_pivot,indef",
+                         [(96, 8, False, False, False), (96, 8, True, False, True),
+                          (100, 8, False, True, True), (70, 6, True, True, False)])
+def test_block_oracle_threaded_is_sequential(orc, n, b, full_block, sign_pivot, indef):
+    """The threaded driver (the pivots of a step on several threads, used for
+    the large cached solves) is bit for bit the sequential oracle, which the
+    pins above tie to the definition: the pivots of a step are disjoint
+    (Sec. 3), so only the order in which they run differs.  Uneven widths
+    (n = 100, b = 8 and n = 70, b = 6) included."""
+    if indef:
+        wl = W.graded_hyperbolic(n, k=50 + n, grade=2.0)
+        G, J = wl.G, wl.J
+    else:
+        G, J = W.graded_cols(n, n, k=60 + n, decades=3.0), None
+    seq = orc.block_jevd(G, J, b=b, full_block=full_block, sign_pivot=sign_pivot)
+    par = orc.block_jevd(G, J, b=b, full_block=full_block, sign_pivot=sign_pivot, nthreads=4)
+    assert seq.status == par.status == 0
+    assert seq.sweeps == par.sweeps and np.array_equal(seq.rot, par.rot)
+    assert np.array_equal(seq.G, par.G) and np.array_equal(seq.V, par.V)
+    assert np.array_equal(seq.lam, par.lam) and np.array_equal(seq.J, par.J)
+    assert seq.extra == par.extra
+
+
+@pytest.mark.parametrize("full_block,sign_pivot,nthreads", [(False, False, 1), (True, False, 3),
+                                                            (False, True, 1), (True, True, 2)])
+def test_block_steps_sample_is_the_first_sweep(orc, full_block, sign_pivot, nthreads):
+    """The bounded sample that the benchmark times (orc_block_steps): all N
+    steps of it are exactly one sweep of the block oracle (same G, bit for
+    bit), and its first k steps are a prefix of that sweep (running the
+    remaining steps would be the same computation)."""
+    n, b = 64, 8
+    wl = W.graded_hyperbolic(n, k=71, grade=2.0)
+    J = wl.J if sign_pivot or full_block else None
+    one = orc.block_jevd(wl.G, J, b=b, full_block=full_block, sign_pivot=sign_pivot,
+                         max_sweeps=1, want_v=False)
+    assert one.status in (0, -3)
+    N = 2 * ((n + 2 * b - 1) // (2 * b))
+    st, Gs = orc.block_steps(wl.G, J, b=b, full_block=full_block, steps=N,
+                             sign_pivot=sign_pivot, nthreads=nthreads)
+    assert st == one.status
+    assert np.array_equal(Gs, one.G)
+    st3, G3 = orc.block_steps(wl.G, J, b=b, full_block=full_block, steps=3,
+                              sign_pivot=sign_pivot, nthreads=nthreads)
+    st3s, G3s = orc.block_steps(wl.G, J, b=b, full_block=full_block, steps=3,
+                                sign_pivot=sign_pivot, nthreads=1)
+    assert np.array_equal(G3, G3s) and not np.array_equal(G3, wl.G)
