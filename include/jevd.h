@@ -61,14 +61,21 @@ enum {
     JEVD_VAR_POINTWISE = 0,       /* 2x2 pivots on single columns */
     JEVD_VAR_BLOCK_ORIENTED = 1,  /* block pivots; annihilate each entry of A_IJ once per step */
     JEVD_VAR_FULL_BLOCK = 2,      /* block pivots; diagonalise every pivot block */
-    JEVD_VAR_AUTO = 3             /* pointwise for small n, block-oriented otherwise */
+    JEVD_VAR_AUTO = 3             /* the variant jevd_autotune recorded for (m, n); when
+                                     the shape has not been tuned, pointwise for n < 2048
+                                     and block-oriented from n = 2048 on */
 };
 
 typedef struct {
     int ordering;      /* JEVD_ORD_*; default JEVD_ORD_MODMODULUS.  Block variants
                           always order block pairs by the modified modulus ordering. */
     int variant;       /* JEVD_VAR_*; default JEVD_VAR_AUTO */
-    int block;         /* block width b of the block variants (16, 32 or 64); 0: choose */
+    int block;         /* block width b of the block variants: 16, 32 or 64 (64 only
+                          with JEVD_PIVOT_NONE); 0: the width jevd_autotune recorded
+                          for (m, n), else 64 for n >= 4096, 32 for n >= 512, 16
+                          below.  The n columns form N = 2 ceil(n / 2b) blocks whose
+                          widths differ by at most one (Sec. 3); any n >= 2 with
+                          N <= n is accepted, sign pivoting needs n divisible by 2b. */
     int max_sweeps;    /* sweep limit, default 50 (>= 1) */
     int max_inner;     /* full block: inner sweep limit per pivot, default 30 */
     int accumulate_v;  /* 0: V := I before the first sweep; 1: V holds a prior
@@ -251,6 +258,39 @@ int jevd_adjoint(jevd_handle_t h, int batch, int m, int n, const double *G, int 
                  const signed char *J, long long sj, const double *lam, long long slam,
                  const double *U, int ldu, long long su, const double *w, long long sw,
                  const double *C, int ldc, long long sc, double *dG, int ldd, long long sd);
+
+/*
+ * Autotuning of the block width and variant (Conclusion: the switching point
+ * between algorithms and block sizes is found by profiling on the machine,
+ * as self-tuning packages do).  jevd_autotune solves a working copy of the
+ * caller's G (device, m x n, ld ldg; not modified) with J, tol and opts
+ * (pivot and precision are kept; variant, block and accumulate_v are
+ * varied/ignored) once for each candidate -- pointwise (FP64 without
+ * pivoting only), and block-oriented and full block at every admissible
+ * b in {16, 32, 64} -- forming V when want_v, and records the fastest
+ * (wall time to convergence) for (m, n) in the process's tune table, which
+ * is also written to the tune file.  *block, *variant, *ms (each may be
+ * NULL) receive the winner (block 0 for pointwise).  Returns JEVD_OK,
+ * JEVD_EINVAL, JEVD_ENOCONV (no candidate converged), JEVD_EHIP or
+ * JEVD_ENOMEM.  Synchronises the handle's stream.
+ *
+ * The tune table maps (m, n) to (block, variant, ms); jacobi_evd and
+ * jevd_validate consult it for opts->block == 0 and JEVD_VAR_AUTO.  The tune
+ * file holds one line "m n block variant ms" per shape; it is
+ * $JEVD_TUNE_FILE, else $HOME/.cache/jevd_tune.txt.  Host-only, no device
+ * work: jevd_tune_file(path) empties the table and loads it from path (NULL:
+ * the default file; a missing file gives an empty table); jevd_tune_lookup
+ * returns JEVD_OK and the record of (m, n), or JEVD_EINVAL if there is none;
+ * jevd_tune_record adds or replaces a record (JEVD_EINVAL for a block width
+ * the shape does not admit, a variant other than pointwise with block 0 or
+ * a block variant, or ms < 0) and rewrites the file.
+ */
+int jevd_autotune(jevd_handle_t h, int m, int n, const double *G, int ldg, const signed char *J,
+                  double tol, const jevd_opts *opts, int want_v, int *block, int *variant,
+                  double *ms);
+int jevd_tune_file(const char *path);
+int jevd_tune_lookup(int m, int n, int *block, int *variant, double *ms);
+int jevd_tune_record(int m, int n, int block, int variant, double ms);
 
 /* Host-only argument check that jacobi_evd runs before any device work
  * (same rules; G, lambda and the handle are not examined).  Returns JEVD_OK

@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjevd.so")
-SOURCES = ["api.hip", "pointwise.hip", "block.hip", "batched.hip", "adjoint.hip", "gemm.hip", "ordering.cpp"]
+SOURCES = ["api.hip", "pointwise.hip", "block.hip", "batched.hip", "adjoint.hip", "gemm.hip", "ordering.cpp",
+           "tune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -3,6 +3,7 @@
 // kernels.
 #include <algorithm>
 #include <cfloat>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -79,6 +80,8 @@ struct jevd_handle_s {
 
     double *vtmp = nullptr;  // V work array of the mixed path when V is not wanted
     size_t capVtmp = 0;
+    double *tuneG = nullptr, *tuneV = nullptr;  // jevd_autotune's working copies
+    size_t capTuneG = 0, capTuneV = 0;
     // adjoint work arrays: K, W, M' (n x n) and T (m x n) per instance
     double *adjK = nullptr, *adjW = nullptr, *adjM = nullptr, *adjT = nullptr;
     size_t capAdjK = 0, capAdjW = 0, capAdjM = 0, capAdjT = 0;
@@ -225,10 +228,14 @@ int jevd_validate(int m, int n, int ldg, const signed char *J, double tol, const
                 for (int i = 0; i < n; ++i)
                     if (J[i] != 1) return JEVD_EINVAL;
         }
-        if (opts->variant == JEVD_VAR_BLOCK_ORIENTED || opts->variant == JEVD_VAR_FULL_BLOCK) {
+        const int variant = (opts->variant == JEVD_VAR_AUTO) ? auto_variant(m, n) : opts->variant;
+        if (variant == JEVD_VAR_BLOCK_ORIENTED || variant == JEVD_VAR_FULL_BLOCK) {
             const int b = opts->block ? opts->block : choose_block_width(m, n);
-            if (!block_shape_supported(m, n, b)) return JEVD_EINVAL;
+            if (!block_options_supported(m, n, b, opts->pivot == JEVD_PIVOT_SIGN)) return JEVD_EINVAL;
         }
+    } else if (auto_variant(m, n) != JEVD_VAR_POINTWISE &&
+               !block_shape_supported(m, n, choose_block_width(m, n))) {
+        return JEVD_EINVAL;
     }
     return JEVD_OK;
 }
@@ -280,6 +287,8 @@ int jevd_destroy(jevd_handle_t h)
         if (h->evApplied[i]) (void)hipEventDestroy(h->evApplied[i]);
     }
     if (h->vtmp) (void)hipFree(h->vtmp);
+    if (h->tuneG) (void)hipFree(h->tuneG);
+    if (h->tuneV) (void)hipFree(h->tuneV);
     if (h->adjK) (void)hipFree(h->adjK);
     if (h->adjW) (void)hipFree(h->adjW);
     if (h->adjM) (void)hipFree(h->adjM);
@@ -510,6 +519,69 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
     }
     if (sweeps) *sweeps = sweeps_done;
     return status;
+}
+
+// Measures the candidate configurations (pointwise; block-oriented and full
+// block at every admissible block width) on a working copy of the caller's
+// G, each solved to convergence with the caller's J, tol and options, and
+// records the fastest for (m, n) in the autotuner table (tune.cpp).
+int jevd_autotune(jevd_handle_t h, int m, int n, const double *G, int ldg, const signed char *J,
+                  double tol, const jevd_opts *opts, int want_v, int *block, int *variant,
+                  double *ms)
+{
+    if (!h || !G) return JEVD_EINVAL;
+    jevd_opts o;
+    fill_defaults(&o);
+    if (opts) o = *opts;
+    o.accumulate_v = 0;
+    int st = jevd_validate(m, n, ldg, J, tol, nullptr, nullptr, m, nullptr, n);
+    if (st) return st;
+    st = grow_device(&h->tuneG, &h->capTuneG, (size_t)m * n);
+    if (st) return st;
+    if (want_v) {
+        st = grow_device(&h->tuneV, &h->capTuneV, (size_t)n * n);
+        if (st) return st;
+    }
+    struct Cand {
+        int variant, block;
+    };
+    std::vector<Cand> cands;
+    if (o.pivot == JEVD_PIVOT_NONE && o.precision == JEVD_PREC_FP64)
+        cands.push_back({JEVD_VAR_POINTWISE, 0});
+    for (int v : {JEVD_VAR_BLOCK_ORIENTED, JEVD_VAR_FULL_BLOCK})
+        for (int b : {16, 32, 64})
+            if (block_options_supported(m, n, b, o.pivot == JEVD_PIVOT_SIGN))
+                cands.push_back({v, b});
+    int best = -1;
+    double best_ms = 0.0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+        jevd_opts oc = o;
+        oc.variant = cands[c].variant;
+        oc.block = cands[c].block;
+        if (oc.variant == JEVD_VAR_POINTWISE && oc.precision != JEVD_PREC_FP64) continue;
+        HIP_TRY(hipMemcpy2DAsync(h->tuneG, sizeof(double) * m, G, sizeof(double) * ldg,
+                                 sizeof(double) * m, n, hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        const auto t0 = std::chrono::steady_clock::now();
+        int sw = 0;
+        const int rc = jacobi_evd(h, m, n, h->tuneG, m, J, tol, &oc, nullptr, nullptr, m,
+                                  want_v ? h->tuneV : nullptr, n, &sw);
+        const double t = std::chrono::duration<double, std::milli>(
+                             std::chrono::steady_clock::now() - t0).count();
+        if (rc == JEVD_EHIP || rc == JEVD_ENOMEM) return rc;
+        if (rc != JEVD_OK) continue;
+        if (best < 0 || t < best_ms) {
+            best = (int)c;
+            best_ms = t;
+        }
+    }
+    if (best < 0) return JEVD_ENOCONV;
+    // the table keeps the record even when the tune file cannot be written
+    (void)jevd_tune_record(m, n, cands[best].block, cands[best].variant, best_ms);
+    if (block) *block = cands[best].block;
+    if (variant) *variant = cands[best].variant;
+    if (ms) *ms = best_ms;
+    return JEVD_OK;
 }
 
 int jevd_canonicalize(jevd_handle_t h, int batch, int m, int n, const double *lam, long long slam,

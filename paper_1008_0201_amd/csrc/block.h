@@ -12,7 +12,8 @@ struct BlockWorkspace {
     double *partial = nullptr;  // split-K partial Grams, per pivot nsplit x (W x W)
     double *vp = nullptr;       // per pivot W x W accumulated transform, row-major
     int *flags = nullptr;       // per pivot: 1 if its transform must be applied
-    size_t capPartial = 0, capVp = 0, capFlags = 0;
+    double2 *vlog = nullptr;    // W = 128: per pivot the log of its inner transforms
+    size_t capPartial = 0, capVp = 0, capFlags = 0, capVlog = 0;
     void *tables = nullptr;     // block and inner orderings (device copies)
     // mixed precision: FP32 iterate and transform, FP64 work arrays
     float *g32 = nullptr, *v32 = nullptr;
@@ -41,6 +42,12 @@ struct BlockRunArgs {
 
 bool block_width_supported(int b);
 bool block_shape_supported(int m, int n, int b);
+bool block_partition_even(int n, int b);
+bool block_options_supported(int m, int n, int b, bool sign_pivot);
+// Autotuner table (tune.cpp): the block width and the variant measured
+// fastest for the shape, or -1 when the shape has not been measured.
+int tuned_block_width(int m, int n);
+int tuned_variant(int m, int n);
 int choose_block_width(int m, int n);
 int auto_variant(int m, int n);
 int run_block(BlockWorkspace *ws, const BlockRunArgs &a, int *sweeps_done);

@@ -1,25 +1,33 @@
-// Block one-sided Jacobi (Sec. 2.2-2.3; Alg. 3.4 with unpivoted Cholesky):
-// block-oriented (BO) and full block (FB), trigonometric or hyperbolic.
+// Block one-sided Jacobi (Sec. 2.2-2.3; Alg. 3.4 with unpivoted Cholesky,
+// or the sign-pivoted Cholesky of Alg. 3.3): block-oriented (BO) and full
+// block (FB), trigonometric or hyperbolic.
 //
-// The n columns form N = n / b block columns of width b; block pairs (I, J)
-// follow the modified modulus ordering over the N blocks (ring order, as in
-// the pointwise path).  One outer step runs three kernels over its N/2
-// pivots G_P = [G_I G_J] (m x W, W = 2b):
+// The n columns form N = 2 ceil(n / 2b) block columns whose widths differ by
+// at most one and are at most b (Sec. 3); block pairs (I, J) follow the
+// modified modulus ordering over the N blocks (ring order, as in the
+// pointwise path).  A pivot G_P = [G_I G_J] has W = 2b positions, block I
+// in positions [0, b) and block J in [b, 2b); a block narrower than b leaves
+// its last positions empty (they load as zero columns, get an identity row
+// and column in the pivot Gram and transform, and are never stored).  One
+// outer step runs three kernels over its N/2 pivots:
 //   k_gram        A_P = G_P^T G_P on FP64 MFMA (v_mfma_f64_16x16x4f64), the
 //                 rows split over several workgroups (split-K); only the
 //                 upper 16 x 16 tiles are formed; partial sums go to a
-//                 workspace and are added in split order by k_pivot_solve.
+//                 workspace and are added in split order by the pivot solve.
 //   k_pivot_solve one workgroup per pivot: skip test, Cholesky A_P = R^T R,
 //                 inner one-sided sweeps on the columns of R (trig or
 //                 hyperbolic by J_P), accumulating V_P; writes V_P
 //                 row-major.  After a Cholesky breakdown the inner sweeps run
 //                 on the columns of G_P in place instead, still accumulating
-//                 V_P, which is then applied to V only.
+//                 V_P, which is then applied to V only.  For W = 128 (b = 64)
+//                 R alone fills the LDS: the inner transforms are logged and
+//                 V_P is formed from the log once R is no longer needed.
 //   k_update      [G_I G_J] <- [G_I G_J] V_P and [V_I V_J] <- [V_I V_J] V_P
-//                 on FP64 MFMA, in place, four tiles of 64 rows per
-//                 workgroup: each wavefront computes (G_P V_P)^T for 16 rows
-//                 of a tile, so that both the loads of G_P and the stores of
-//                 the result are 16 consecutive rows per column.
+//                 on FP64 MFMA, in place, four row tiles per workgroup: each
+//                 wavefront computes (G_P V_P)^T for 16 rows of a tile, so
+//                 that both the loads of G_P and the stores of the result are
+//                 16 consecutive rows per column.
+#include <utility>
 #include <vector>
 
 #include "../../include/jevd.h"
@@ -60,10 +68,17 @@ template <> struct Mfma<float> {
     __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
 };
 
-// Global column of pivot-local column k of the block pair (I, J).
-__device__ __forceinline__ int pivot_col(int k, int2 IJ, int b)
+// A pivot: the first column and the width of its two blocks (x, y: block
+// I; z, w: block J).  Position k (0 <= k < 2b) of the pivot is column x + k
+// for k < y, column z + k - b for b <= k < b + w, and empty otherwise.
+__device__ __forceinline__ int pivot_col(int k, int4 d, int b)
 {
-    return k < b ? IJ.x * b + k : IJ.y * b + (k - b);
+    if (k < b) return k < d.y ? d.x + k : -1;
+    return (k - b) < d.w ? d.z + (k - b) : -1;
+}
+__device__ __forceinline__ bool pivot_real(int k, int4 d, int b)
+{
+    return k < b ? k < d.y : (k - b) < d.w;
 }
 
 // ------------------------------------------------------------------ k_gram
@@ -87,10 +102,6 @@ __host__ __device__ constexpr int upper_tile_j(int NT, int t)
     return it + t;
 }
 
-// The MFMAs of one staged slab for wavefront WV: tiles WV, WV + 4, ... of
-// the upper triangle (past the last tile, tile 0 again), all indices known at
-// compile time.  Each k-step reads the NT column-block operands once; the
-// reads of step k + 1 are issued before the MFMAs of step k.
 // x, or +0 when !keep, without a branch (an all-ones or all-zeros mask on
 // the bits).
 __device__ __forceinline__ double zero_unless(double x, bool keep)
@@ -104,6 +115,8 @@ __device__ __forceinline__ float zero_unless(float x, bool keep)
     return __int_as_float(__float_as_int(x) & m);
 }
 
+// Tile WV + 4 Q of the upper triangle (past the last tile: tile 0 again,
+// computed but not stored), known at compile time.
 template <int NT, int WV, int Q>
 struct GramTile {
     static constexpr int t = (WV + 4 * Q < NT * (NT + 1) / 2) ? WV + 4 * Q : 0;
@@ -111,6 +124,16 @@ struct GramTile {
     static constexpr int j = upper_tile_j(NT, t);
 };
 
+template <int NT, int WV, class T, class Acc, size_t... Q>
+__device__ __forceinline__ void gram_mfmas(const T *cur, Acc *acc, std::index_sequence<Q...>)
+{
+    ((acc[Q] = mfma16x16x4(cur[GramTile<NT, WV, Q>::i], cur[GramTile<NT, WV, Q>::j], acc[Q])), ...);
+}
+
+// The MFMAs of one staged slab for wavefront WV: tiles WV, WV + 4, ... of
+// the upper triangle, all indices known at compile time.  Each k-step reads
+// the NT column-block operands once; the reads of step k + 1 are issued
+// before the MFMAs of step k.
 template <int W, class T, int KR, int LDC, int WV>
 __device__ __forceinline__ void gram_slab(const T *st, int lane, typename Mfma<T>::acc *acc)
 {
@@ -127,65 +150,63 @@ __device__ __forceinline__ void gram_slab(const T *st, int lane, typename Mfma<T
 #pragma unroll
             for (int c = 0; c < NT; ++c) nxt[c] = row[(k + 4) * LDC + c * 16];
         }
-        static_assert(TPW <= 3, "tiles per wavefront");
-        acc[0] = mfma16x16x4(cur[GramTile<NT, WV, 0>::i], cur[GramTile<NT, WV, 0>::j], acc[0]);
-        if constexpr (TPW > 1)
-            acc[1] = mfma16x16x4(cur[GramTile<NT, WV, 1>::i], cur[GramTile<NT, WV, 1>::j], acc[1]);
-        if constexpr (TPW > 2)
-            acc[2] = mfma16x16x4(cur[GramTile<NT, WV, 2>::i], cur[GramTile<NT, WV, 2>::j], acc[2]);
+        gram_mfmas<NT, WV>(cur, acc, std::make_index_sequence<TPW>());
 #pragma unroll
         for (int c = 0; c < NT; ++c) cur[c] = nxt[c];
     }
 }
 
-// 32-row slabs of G_P are staged transposed in LDS (row pitch W+1), double
+// Slabs of 32 rows of G_P (16 at W = 128, whose nine tiles per wavefront
+// take the registers) are staged transposed in LDS (row pitch W+1), double
 // buffered: the loads of slabs s+1 and s+2 are in flight in registers while
 // the MFMAs of slab s run, with one barrier per slab.  Every wavefront runs the
 // same number of tiles (the upper tiles padded with repeats that are not
 // stored) and the tile indices are wave-uniform, so the k-loop has no
-// branches and the LDS reads of a slab overlap its MFMAs.  The step's
-// 1024 workgroups are resident at once only with four per CU, hence the
-// register budget of four wavefronts per SIMD (the LDS allows four too).
-// The block width b is W / 2 (the argument is kept for the launch shape).
+// branches and the LDS reads of a slab overlap its MFMAs.  Empty pivot
+// positions load column 0 of their block and are stored to LDS as zeros.
 template <int W, class T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gram(
-    const T *__restrict__ G, int m, long ldg, int b, const int2 *__restrict__ piv,
-    int rows_per_split, double *__restrict__ partial)
+__device__ __forceinline__ void gram_body(const T *__restrict__ G, int m, long ldg,
+                                          const int4 *__restrict__ piv, int rows_per_split,
+                                          double *__restrict__ partial)
 {
-    constexpr int KR = 32;                    // rows staged per slab
-    constexpr int LDC = W + 1;                // padded LDS row (doubles)
+    constexpr int KR = W <= 64 ? 32 : 16;     // rows staged per slab
+    constexpr int LDC = W + 1;                // padded LDS row (elements)
     constexpr int NT = W / 16;
     constexpr int NUP = NT * (NT + 1) / 2;    // upper tiles, diagonal included
     constexpr int TPW = (NUP + 3) / 4;        // tiles per wavefront
     constexpr int EPT = KR * W / 256;         // staged elements per thread
+    static_assert(EPT <= 32, "one mask bit per staged element");
     __shared__ T st[2][KR * LDC];             // st[buf][kr][c] = G_P[r0 + kr][c]
     const int pv = blockIdx.x, split = blockIdx.y;
-    const int2 IJ = piv[pv];
+    const int4 d = piv[pv];
     const int r_begin = split * rows_per_split;
     const int r_end = min(m, r_begin + rows_per_split);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-
-    // tile wave + 4 q of the upper triangle, row-major; past the last tile
-    // the wavefront repeats tile 0 and does not store it
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     typename Mfma<T>::acc acc[TPW];
 #pragma unroll
     for (int q = 0; q < TPW; ++q) acc[q] = typename Mfma<T>::acc{0, 0, 0, 0};
 
     // element u of this thread's slab share: row kr = tid % KR of pivot
-    // column c0 + CS u, c0 = tid / KR.  CS divides b = W / 2, so the column
-    // lies in block I for u < b / CS and in block J after: a wave-uniform
-    // column base per u plus one 32-bit per-lane offset.
+    // position c0 + CS u, c0 = tid / KR.  CS divides b = W / 2, so positions
+    // CS u .. CS u + CS - 1 lie in one block: a wave-uniform block base per
+    // u and a 32-bit per-lane column offset (0 for an empty position).
     constexpr int CS = 256 / KR;
     constexpr int HB = W / 2;
     static_assert(HB % CS == 0, "slab columns must not straddle the blocks");
     const int kr = threadIdx.x % KR, c0 = threadIdx.x / KR;
-    const unsigned lane_off = (unsigned)c0 * (unsigned)ldg;
     const T *colb[EPT];
+    unsigned coff[EPT];
+    unsigned live_cols = 0;
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
         const int c = CS * u;
-        colb[u] = G + (size_t)(c < HB ? IJ.x * HB + c : IJ.y * HB + (c - HB)) * ldg;
+        const bool in_i = c < HB;
+        const int o = (in_i ? c : c - HB) + c0, w = in_i ? d.y : d.w;
+        const bool real = o < w;
+        colb[u] = G + (size_t)(in_i ? d.x : d.z) * ldg;
+        coff[u] = (unsigned)(real ? o : 0) * (unsigned)ldg;
+        live_cols |= (unsigned)real << u;
     }
     const int st_off = kr * LDC + c0;
     // Two slabs of loads in flight: register sets ra and rb take alternate
@@ -195,16 +216,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // zeros; the select sits at the store, so that the loads stay in flight
     // across the MFMAs.
     auto load_slab = [&](T *reg, int r0) {
-        const unsigned rr = lane_off + (unsigned)min(r0 + kr, r_end - 1);
+        const unsigned rr = (unsigned)min(r0 + kr, r_end - 1);
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) reg[u] = colb[u][rr];
+        for (int u = 0; u < EPT; ++u) reg[u] = colb[u][coff[u] + rr];
     };
     auto run_slab = [&](T *reg, int r0, int buf) {
         // zeroing by a bit mask: a select here was turned into a branch
         // around the store, which left the loads counted as in flight
         const bool live = r0 + kr < r_end;
 #pragma unroll
-        for (int u = 0; u < EPT; ++u) st[buf][st_off + CS * u] = zero_unless(reg[u], live);
+        for (int u = 0; u < EPT; ++u)
+            st[buf][st_off + CS * u] = zero_unless(reg[u], live && ((live_cols >> u) & 1u));
         __syncthreads();
         load_slab(reg, r0 + 2 * KR);
         switch (wv) {
@@ -236,6 +258,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
 }
 
+// The step's workgroups (about 1024) are resident at once with four per CU
+// for W <= 64, hence the register budget of four wavefronts per SIMD; at
+// W = 128 two workgroups fit a CU (66 KiB of LDS each) and the wavefronts
+// hold nine upper tiles each, so the budget is two per SIMD.
+template <int W, class T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_gram(
+    const T *__restrict__ G, int m, long ldg, const int4 *__restrict__ piv, int rows_per_split,
+    double *__restrict__ partial)
+{
+    gram_body<W, T>(G, m, ldg, piv, rows_per_split, partial);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_gram128(
+    const T *__restrict__ G, int m, long ldg, const int4 *__restrict__ piv, int rows_per_split,
+    double *__restrict__ partial)
+{
+    gram_body<128, T>(G, m, ldg, piv, rows_per_split, partial);
+}
+
 // ---------------------------------------------------------- k_pivot_solve
 // Inner orderings over the W = 2b columns of a pivot, in closed form (no
 // table reads on the critical path of an inner step):
@@ -262,7 +304,7 @@ __device__ __forceinline__ int2 inner_pair(int all_pairs, int W, int s, int r)
 template <int NW>
 __device__ void inner_sweep_global(double *X, long ldx, int len, double *Y, long ldy, int ylen,
                                    const signed char *JP, int all_pairs, int W, double tol,
-                                   int2 IJ, int b, unsigned long long &rot,
+                                   int4 d, int b, unsigned long long &rot,
                                    unsigned long long &ncl, int *bad)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -270,8 +312,10 @@ __device__ void inner_sweep_global(double *X, long ldx, int len, double *Y, long
     for (int s = 0; s < nsteps; ++s) {
         for (int e = wave; e < npairs; e += NW) {
             const int2 pq = inner_pair(all_pairs, W, s, e);
-            double *xp = X + (size_t)pivot_col(pq.x, IJ, b) * ldx;
-            double *xq = X + (size_t)pivot_col(pq.y, IJ, b) * ldx;
+            const int cp = pivot_col(pq.x, d, b), cq = pivot_col(pq.y, d, b);
+            if (cp < 0 || cq < 0) continue;   // an empty position: nothing to rotate
+            double *xp = X + (size_t)cp * ldx;
+            double *xq = X + (size_t)cq * ldx;
             double app = 0.0, aqq = 0.0, apq = 0.0;
             for (int r = lane; r < len; r += 64) {
                 const double x = xp[r], y = xq[r];
@@ -316,7 +360,7 @@ struct PivotSolveArgs {
     const double *partial;
     int nsplit;
     signed char *J;  // device signs (null: J = I); rewritten by the sign pivoting
-    const int2 *piv;
+    const int4 *piv;
     int b;
     double tol;
     int all_pairs, full_block, max_inner;
@@ -329,6 +373,11 @@ struct PivotSolveArgs {
     int m;
     long ldg;
     int sign_pivot;  // Alg. 3.3 instead of the unpivoted Cholesky
+    // W = 128: the inner transforms of each pivot, (c, s) per pair and step
+    // (c negated for a hyperbolic transform; (1, 0): none), log_stride
+    // entries per pivot
+    double2 *vlog;
+    long log_stride;
 };
 
 // LDS pitch of the factor R: one more than W (bank spread when the lanes of
@@ -362,11 +411,14 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     __shared__ int s_need, s_bad, s_npos;
     __shared__ unsigned long long s_rot[NW], s_cl[NW];
     const int pv = blockIdx.x;
-    const int2 IJ = a.piv[pv];
+    const int4 d = a.piv[pv];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int b = a.b;
 
-    if (tid < W) JP[tid] = a.J ? a.J[pivot_col(tid, IJ, b)] : (signed char)1;
+    if (tid < W) {
+        const int c = pivot_col(tid, d, b);
+        JP[tid] = (a.J && c >= 0) ? a.J[c] : (signed char)1;
+    }
     if (tid == 0) {
         s_need = 0;
         s_bad = 0;
@@ -405,7 +457,11 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int e = e0 + q * kPivotThreads;
-            if (e < W * W) A[(e / W) * P + (e % W)] = acc[q];
+            // an empty position has a zero Gram row and column: its diagonal
+            // entry becomes 1 (an identity row and column of A_P)
+            if (e < W * W)
+                A[(e / W) * P + (e % W)] =
+                    (e / W == e % W && !pivot_real(e % W, d, b)) ? 1.0 : acc[q];
         }
     }
     __syncthreads();
@@ -668,7 +724,7 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
             }
         } else {
             // G_P is transformed in place; V_P collects the transforms for V
-            inner_sweep_global<NW>(a.G, a.ldg, a.m, VP, P, W, JP, a.all_pairs, W, a.tol, IJ, b,
+            inner_sweep_global<NW>(a.G, a.ldg, a.m, VP, P, W, JP, a.all_pairs, W, a.tol, d, b,
                                    rot_it, ncl, &bad);
         }
         rot += rot_it;
@@ -713,95 +769,511 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
             const int r = e / W, c = e % W;
             out[(sp ? s_perm[r] : r) * W + c] = VP[c * P + r];
         }
-        if (sp && a.J && !s_bad && tid < W) a.J[pivot_col(tid, IJ, b)] = JS[tid];
+        if (sp && a.J && !s_bad && tid < W && pivot_real(tid, d, b)) a.J[pivot_col(tid, d, b)] = JS[tid];
+    }
+}
+
+// ------------------------------------------------ k_pivot_solve_log (W = 128)
+// The pivot solve for W = 128 (b = 64).  R (W x W, pitch W + 1) alone fills
+// 129 KiB of the LDS, so V_P is not kept beside it: the inner steps log
+// their transforms (one 16-byte entry per pair and step, in global memory),
+// and when the inner sweeps are done the LDS of R holds V_P (row-major),
+// which the log is replayed on, one thread per row: every row of V_P
+// receives the column transforms in the order they were applied to R, with
+// the same arithmetic (rotate_elems).  The Cholesky factorisation runs in
+// place in the upper triangle of A (the diagonal keeps the pivot d_j until
+// the end, when it becomes sqrt(d_j)).  In an inner step lane k of every
+// wavefront owns pair k (W/2 = 64 pairs) and wavefront w rows
+// [w W/4, (w+1) W/4) of it; the partial dot products meet in LDS as in
+// k_pivot_solve.  Unpivoted Cholesky only (the sign pivoting of Alg. 3.3
+// runs at W <= 64).  After a breakdown V_P is accumulated in LDS directly
+// while the inner sweeps run on G_P (R is not needed then).
+constexpr int kLogThreads = 256;
+
+template <int W>
+__global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs a)
+{
+    constexpr int NW = kLogThreads / 64;
+    constexpr int P = W + 1;
+    constexpr int NP = W / 2;          // pairs per inner step: lane k owns pair k
+    constexpr int RPW = W / NW;        // rows of R per wavefront
+    constexpr int RB = 8;              // rows summed as one pairwise subtree
+    static_assert(NP == 64 && RPW % RB == 0, "one lane per pair");
+    __shared__ double A[W * P];        // Gram, then R (upper), then V_P
+    __shared__ double red[NW * 3 * NP];  // partial dots; in the replay, staged log entries
+    __shared__ double dsh[W];          // Cholesky pivots d_j
+    __shared__ signed char JP[W];
+    __shared__ int s_need, s_bad;
+    __shared__ unsigned long long s_rot[NW], s_cl[NW];
+    const int pv = blockIdx.x;
+    const int4 d = a.piv[pv];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = a.b;
+
+    if (tid < W) {
+        const int c = pivot_col(tid, d, b);
+        JP[tid] = (a.J && c >= 0) ? a.J[c] : (signed char)1;
+    }
+    if (tid == 0) {
+        s_need = 0;
+        s_bad = 0;
+    }
+    // A_P: the split partials (upper tiles) added in split order, mirrored
+    // to the lower part; empty positions get an identity row and column
+    const double *base = a.partial + (size_t)pv * a.nsplit * W * W;
+    for (int e0 = tid; e0 < W * W; e0 += 4 * kLogThreads) {
+        int off[4];
+        double acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * kLogThreads;
+            int r = e % W, c = e / W;
+            if ((r / 16) > (c / 16) || ((r / 16) == (c / 16) && r > c)) {
+                const int t = r;
+                r = c;
+                c = t;
+            }
+            off[q] = (e < W * W) ? c * W + r : 0;
+            acc[q] = 0.0;
+        }
+        for (int sp0 = 0; sp0 < a.nsplit; sp0 += 8) {
+            double v[4][8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    v[q][u] = (sp0 + u < a.nsplit) ? base[(size_t)(sp0 + u) * W * W + off[q]] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (sp0 + u < a.nsplit) acc[q] += v[q][u];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = e0 + q * kLogThreads;
+            if (e < W * W)
+                A[(e / W) * P + (e % W)] =
+                    (e / W == e % W && !pivot_real(e % W, d, b)) ? 1.0 : acc[q];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < W * W; e += kLogThreads) {
+        const int r = e % W, c = e / W;
+        const double x = A[c * P + r];
+        if (!isfinite(x)) s_bad = 1;
+        if (r < c && (a.all_pairs || (r < b && c >= b))) {
+            const double arr = A[r * P + r], acc2 = A[c * P + c];
+            if (arr != 0.0 && acc2 != 0.0 && fabs(x) > a.tol * sqrt(arr) * sqrt(acc2)) s_need = 1;
+        }
+    }
+    __syncthreads();
+    if (s_bad) {
+        if (tid == 0) {
+            a.ctr->nonfinite = 1u;
+            a.flag[pv] = 0;
+        }
+        return;
+    }
+    if (!s_need) {
+        if (tid == 0) a.flag[pv] = 0;
+        return;
+    }
+    // Cholesky A_P = R^T R in place, right-looking, one barrier per column:
+    // with row j of R final (r_jl = a_jl / sqrt(d_j) in the upper triangle),
+    // the step finishes row j + 1 (d_{j+1} = a_{j+1,j+1} - r_{j,j+1}^2,
+    // r_{j+1,l} = (a_{j+1,l} - r_{j,j+1} r_jl) / sqrt(d_{j+1})) and subtracts
+    // r_ji r_jl from the entries (i, l), j + 2 <= i <= l, of the rows below;
+    // the two touch different rows.  The pivots d_j go to dsh (R's diagonal
+    // is sqrt(d_j)).  Every thread computes d_{j+1} from LDS after the
+    // barrier, so a breakdown is seen by all at once.
+    bool broke = false;
+    {
+        const double d0 = A[0];
+        if (!(d0 > 0.0)) {
+            broke = true;
+        } else {
+            const double r00 = sqrt(d0);
+            for (int l = 1 + tid; l < W; l += kLogThreads) A[l * P] = A[l * P] / r00;
+            if (tid == 0) dsh[0] = d0;
+        }
+        __syncthreads();
+    }
+    for (int j = 0; j + 1 < W && !broke; ++j) {
+        const int j1 = j + 1;
+        const double rj1 = A[j1 * P + j];
+        const double d1 = A[j1 * P + j1] - rj1 * rj1;
+        if (!(d1 > 0.0)) {
+            broke = true;
+            break;
+        }
+        const double r11 = sqrt(d1);
+        for (int l = j1 + 1 + tid; l < W; l += kLogThreads)
+            A[l * P + j1] = (A[l * P + j1] - rj1 * A[l * P + j]) / r11;
+        // the trailing rows over a 16 x 16 thread grid; row j's entries of
+        // this thread's columns i are read once
+        const int tl = tid >> 4, ti = tid & 15;
+        double ri[W / 16];
+#pragma unroll
+        for (int u = 0; u < W / 16; ++u) {
+            const int i = j + 2 + ti + 16 * u;
+            ri[u] = (i < W) ? A[i * P + j] : 0.0;
+        }
+        for (int l = j + 2 + tl; l < W; l += 16) {
+            const double rl = A[l * P + j];
+#pragma unroll
+            for (int u = 0; u < W / 16; ++u) {
+                const int i = j + 2 + ti + 16 * u;
+                if (i <= l) A[l * P + i] -= ri[u] * rl;
+            }
+        }
+        if (tid == 0) dsh[j1] = d1;
+        __syncthreads();
+    }
+    if (broke && !a.G) {
+        // no FP64 copy of G to transform in place (the FP32 sweeps): the
+        // pivot is left to the FP64 sweeps that follow
+        if (tid == 0) {
+            atomicAdd(&a.ctr->breakdowns, 1ull);
+            a.flag[pv] = 0;
+        }
+        return;
+    }
+    unsigned long long rot = 0, ncl = 0;
+    int bad = 0;
+    const int sweeps = a.full_block ? a.max_inner : 1;
+    const int nsteps = inner_steps(a.all_pairs, W);
+    double2 *log = a.vlog + (size_t)pv * a.log_stride;
+    int logged = 0;   // inner sweeps in the log
+    if (!broke) {
+        // R: the diagonal becomes sqrt(d_j), the strict lower triangle zero
+        for (int e = tid; e < W * W; e += kLogThreads) {
+            const int r = e % W, c = e / W;
+            if (r == c) A[c * P + r] = sqrt(dsh[c]);
+            else if (r > c) A[c * P + r] = 0.0;
+        }
+        __syncthreads();
+        const int r0 = wave * RPW;
+        // I x J steps (block-oriented after the first step of a sweep): lane k
+        // pairs column k of block I with a column of block J that changes
+        // every step, so column k stays in registers for the whole inner
+        // sweep (and is not written back: R is not needed after the sweeps)
+        const bool keep_x = !a.all_pairs;
+        double xr[RPW];
+        if (keep_x) {
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) xr[r] = A[lane * P + r0 + r];
+        }
+        for (int it = 0; it < sweeps; ++it) {
+            unsigned long long rot_it = 0;
+            for (int s = 0; s < nsteps; ++s) {
+                const int2 pq = inner_pair(a.all_pairs, W, s, lane);
+                double *yp = A + pq.x * P + r0, *yq = A + pq.y * P + r0;
+                double yr[RPW];
+                if (!keep_x) {
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) xr[r] = yp[r];
+                }
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) yr[r] = yq[r];
+                // partial dot products over this wavefront's rows: pairwise
+                // subtrees of RB rows, then a pairwise tree over the subtrees
+                double pxx[RPW / RB], pyy[RPW / RB], pxy[RPW / RB];
+#pragma unroll
+                for (int g = 0; g < RPW / RB; ++g) {
+                    double sxx[RB], syy[RB], sxy[RB];
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) {
+                        const double x = xr[g * RB + r], y = yr[g * RB + r];
+                        sxx[r] = x * x;
+                        syy[r] = y * y;
+                        sxy[r] = x * y;
+                    }
+#pragma unroll
+                    for (int h = RB / 2; h > 0; h /= 2)
+#pragma unroll
+                        for (int r = 0; r < h; ++r) {
+                            sxx[r] += sxx[r + h];
+                            syy[r] += syy[r + h];
+                            sxy[r] += sxy[r + h];
+                        }
+                    pxx[g] = sxx[0];
+                    pyy[g] = syy[0];
+                    pxy[g] = sxy[0];
+                }
+#pragma unroll
+                for (int h = RPW / RB / 2; h > 0; h /= 2)
+#pragma unroll
+                    for (int g = 0; g < h; ++g) {
+                        pxx[g] += pxx[g + h];
+                        pyy[g] += pyy[g + h];
+                        pxy[g] += pxy[g + h];
+                    }
+                red[(wave * 3 + 0) * NP + lane] = pxx[0];
+                red[(wave * 3 + 1) * NP + lane] = pyy[0];
+                red[(wave * 3 + 2) * NP + lane] = pxy[0];
+                __syncthreads();
+                // (w0 + w1) + (w2 + w3): the same order in every wavefront
+                static_assert(NW == 4, "four wavefronts");
+                double t[3][NW];
+#pragma unroll
+                for (int w = 0; w < NW; ++w)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) t[k][w] = red[(w * 3 + k) * NP + lane];
+                const double app = (t[0][0] + t[0][1]) + (t[0][2] + t[0][3]);
+                const double aqq = (t[1][0] + t[1][1]) + (t[1][2] + t[1][3]);
+                const double apq = (t[2][0] + t[2][1]) + (t[2][2] + t[2][3]);
+                bool act = true;
+                if (!finite3(app, aqq, apq)) {
+                    bad = 1;
+                    act = false;
+                }
+                act = act && needs_rotation(app, aqq, apq, a.tol);
+                const bool same = act ? (JP[pq.x] == JP[pq.y]) : true;
+                double c = 1.0, sn = 0.0;
+                if (act && transform_params(app, aqq, apq, same, c, sn) && wave == 0) ++ncl;
+                if (wave == 0)
+                    log[((size_t)it * nsteps + s) * NP + lane] =
+                        act ? make_double2(same ? c : -c, sn) : make_double2(1.0, 0.0);
+                if (act) {
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) rotate_elems(xr[r], yr[r], c, sn, same);
+                    if (!keep_x) {
+#pragma unroll
+                        for (int r = 0; r < RPW; ++r) yp[r] = xr[r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) yq[r] = yr[r];
+                    if (wave == 0) ++rot_it;
+                }
+                __syncthreads();
+            }
+            ++logged;
+            rot += rot_it;
+            const double wr = wave_sum((double)rot_it);
+            if (lane == 0) s_rot[wave] = (unsigned long long)wr;
+            __syncthreads();
+            // only wavefront 0 counted, so its total is the step's
+            const unsigned long long tot = s_rot[0];
+            __syncthreads();
+            if (tot == 0) break;
+        }
+        // V_P := I (row-major, pitch P), then the logged transforms are
+        // replayed on its rows.  Lanes l and l + 32 of wavefront w own row
+        // 32 w + l mod 32 and take the first and the second half of each
+        // step's pairs: the pairs of a step are disjoint, and the LDS accesses
+        // of one wavefront complete in order, so the halves need no barrier
+        // between steps.  The log passes through LDS (the red area) RC steps
+        // at a time, the next chunk loaded while the current one is replayed;
+        // its global writes were made visible first.
+        __threadfence();
+        for (int e = tid; e < W * W; e += kLogThreads) {
+            const int r = e / W, c = e % W;
+            A[r * P + c] = (r == c) ? 1.0 : 0.0;
+        }
+        constexpr int RC = kLogThreads / NP;   // steps per chunk: one entry per thread
+        static_assert(RC * NP == kLogThreads && RC * NP * 2 <= NW * 3 * NP, "log chunk in red");
+        double2 *stage = (double2 *)red;
+        const long total = (long)logged * nsteps;   // logged steps
+        const int row = wave * 32 + (lane & 31), half = lane >> 5;
+        double *vr = A + row * P;
+        double2 nxt = (total * NP > tid) ? log[tid] : make_double2(1.0, 0.0);
+        for (long c0 = 0; c0 < total; c0 += RC) {
+            __syncthreads();   // the previous chunk is no longer read
+            stage[tid] = nxt;
+            __syncthreads();
+            const long e_next = (c0 + RC) * NP + tid;
+            if (e_next < total * NP) nxt = log[e_next];
+            for (int sc = 0; sc < RC && c0 + sc < total; ++sc) {
+                const int s = (int)((c0 + sc) % nsteps);   // step within its inner sweep
+                const double2 *le = stage + sc * NP + half * (NP / 2);
+#pragma unroll 4
+                for (int i = 0; i < NP / 2; ++i) {
+                    const double2 e = le[i];
+                    if (e.x == 1.0 && e.y == 0.0) continue;
+                    const int2 pq = inner_pair(a.all_pairs, W, s, half * (NP / 2) + i);
+                    double x = vr[pq.x], y = vr[pq.y];
+                    rotate_elems(x, y, fabs(e.x), e.y, e.x > 0.0);
+                    vr[pq.x] = x;
+                    vr[pq.y] = y;
+                }
+            }
+        }
+        __syncthreads();
+    } else {
+        // G_P is transformed in place; V_P (column-major, pitch P) collects
+        // the transforms for V
+        for (int e = tid; e < W * W; e += kLogThreads) {
+            const int r = e % W, c = e / W;
+            A[c * P + r] = (r == c) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        for (int it = 0; it < sweeps; ++it) {
+            unsigned long long rot_it = 0;
+            inner_sweep_global<NW>(a.G, a.ldg, a.m, A, P, W, JP, a.all_pairs, W, a.tol, d, b,
+                                   rot_it, ncl, &bad);
+            rot += rot_it;
+            const double wr = wave_sum((double)rot_it);
+            if (lane == 0) s_rot[wave] = (unsigned long long)wr;
+            __syncthreads();
+            unsigned long long tot = 0;
+            for (int w = 0; w < NW; ++w) tot += s_rot[w];
+            __syncthreads();
+            if (tot == 0) break;
+        }
+    }
+    {
+        const double wr = wave_sum((double)rot), wc = wave_sum((double)ncl);
+        if (lane == 0) {
+            s_rot[wave] = (unsigned long long)wr;
+            s_cl[wave] = (unsigned long long)wc;
+        }
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+    unsigned long long tot = 0, totc = 0;
+    for (int w = 0; w < NW; ++w) {
+        tot += s_rot[w];
+        totc += s_cl[w];
+    }
+    if (tid == 0) {
+        if (tot) atomicAdd(&a.ctr->rotations, tot);
+        if (totc) atomicAdd(&a.ctr->clamps, totc);
+        if (broke) atomicAdd(&a.ctr->breakdowns, 1ull);
+        if (s_bad) a.ctr->nonfinite = 1u;
+        a.flag[pv] = (tot > 0 && !s_bad) ? (broke ? 2 : 1) : 0;
+    }
+    if (tot > 0) {
+        double *out = a.vpt + (size_t)pv * W * W;
+        for (int e = tid; e < W * W; e += kLogThreads) {
+            const int r = e / W, c = e % W;
+            out[e] = broke ? A[c * P + r] : A[r * P + c];
+        }
     }
 }
 
 // ---------------------------------------------------------------- k_update
-// One workgroup handles TILES consecutive 64-row tiles of one pivot (of G,
-// or of V): V_P is staged in LDS once, and the loads of tile t+1 are in
-// flight while the MFMAs of tile t run.
-constexpr int kUpdateTiles = 4;
+// One workgroup (four wavefronts) handles consecutive 64-row tiles of one
+// pivot (of G, or of V): V_P is staged in LDS once, and the loads of tile
+// t+1 are in flight while the MFMAs of tile t run.  At W = 128 V_P takes
+// 144 KiB of LDS, so one workgroup fills a CU: its wavefronts then have the
+// whole register file (one per SIMD), which the 32 k-steps of operands of
+// two tiles need, and eight tiles per workgroup amortise the staging.
+template <int W> struct UpdateShape {
+    static constexpr int threads = 256;
+    static constexpr int tile_rows = 64;   // 16 rows per wavefront
+    static constexpr int tiles = W <= 64 ? 4 : 8;
+    static constexpr int group_rows = tile_rows * tiles;
+};
 
 // The row tiles of one k_update workgroup: V_P (W x W, FP64 row-major) is
 // staged in S (row pitch W + 16), then the wavefront transforms rows
-// wrow + lane % 16 + 64 t.  FULL: all rows of the workgroup exist, so no
+// wrow + lane % 16 + TR t.  FULL: all rows of the workgroup exist, so no
 // load or store is predicated and the compiler waits for the prefetched
 // operands alone (a predicated memory operation leaves the count of those in
 // flight unknown, and it then waits for all of them, the stores included).
 // Otherwise the loads are clamped to the last row (the lanes past it only
 // feed result rows that are not stored) and the stores are guarded.
-template <int W, class T, bool FULL>
+// UNEVEN: the pivot may have empty positions; their loads read column 0 of
+// the block (the row of V_P for an empty position is e_k, so the value only
+// meets zeros in real output columns) and their results are not stored.
+template <int W, class T, bool FULL, bool UNEVEN>
 __device__ __forceinline__ void update_tiles(T *__restrict__ X, long ld, int rows, int wrow,
-                                             int lane, int2 IJ, int b,
-                                             const double *__restrict__ src, T *S)
+                                             int lane, int4 d, const double *__restrict__ src, T *S)
 {
+    constexpr int NTH = UpdateShape<W>::threads;
+    constexpr int TR = UpdateShape<W>::tile_rows;
+    constexpr int kUpdateTiles = UpdateShape<W>::tiles;
     constexpr int KS = W / 4;   // k-steps of the MFMA
     constexpr int NT = W / 16;  // output column tiles
     constexpr int SP = W + 16;
-    constexpr int SE = W * W / 256;
+    constexpr int SE = W * W / NTH;
+    constexpr int HB = W / 2;
     auto clamp_row = [&](int r) { return FULL ? r : min(r, rows - 1); };
-    // Pivot columns 4g .. 4g+3 lie in one block (b is a multiple of 4), so
-    // the column of lane l in k-step ks is the wave-uniform pivot_col(4 ks)
-    // plus l / 16: wave-uniform column bases and one 32-bit per-lane offset.
-    const unsigned lane_off = (unsigned)(lane / 16) * (unsigned)ld;
+    // Pivot positions 4g .. 4g+3 lie in one block (b is a multiple of 4), so
+    // the element of lane l in k-step ks is at a wave-uniform base (the block,
+    // then column 4 ks - bp of it) plus a per-lane byte offset that is the
+    // same for every k-step of a tile: (l / 16) columns and the row.  With
+    // empty positions (UNEVEN) the lane part is formed per k-step instead
+    // (column 0 of the block for an empty position).
+    const int lq = lane / 16;
     const int row0 = wrow + lane % 16;
+    const char *xI = (const char *)(X + (size_t)d.x * ld), *xJ = (const char *)(X + (size_t)d.z * ld);
+    const size_t colb = (size_t)ld * sizeof(T);   // bytes per column
+    auto kbase = [&](int ks) -> const char * {
+        return (4 * ks < HB) ? xI + (size_t)(4 * ks) * colb : xJ + (size_t)(4 * ks - HB) * colb;
+    };
+    // the element of (column 4 ks - bp + l / 16, row): kbase(ks) plus a
+    // 32-bit byte offset, or with empty positions a signed 64-bit one (an
+    // empty position reads column 0 of the block, behind kbase(ks))
+    auto kload = [&](int ks, int row) -> T {
+        if constexpr (!UNEVEN) {
+            const unsigned off = ((unsigned)lq * (unsigned)ld + (unsigned)row) * (unsigned)sizeof(T);
+            return *(const T *)(kbase(ks) + off);
+        } else {
+            const bool in_i = 4 * ks < HB;
+            const int o = (in_i ? 4 * ks : 4 * ks - HB) + lq;
+            const bool real = o < (in_i ? d.y : d.w);
+            const long back = real ? (long)lq : -(long)(in_i ? 4 * ks : 4 * ks - HB);
+            return *(const T *)(kbase(ks) + (back * ld + row) * (long)sizeof(T));
+        }
+    };
 
     // all loads of V_P and of the first tile in flight before the LDS stores
     double sv[SE];
 #pragma unroll
-    for (int i = 0; i < SE; ++i) sv[i] = src[threadIdx.x + 256 * i];
+    for (int i = 0; i < SE; ++i) sv[i] = src[threadIdx.x + NTH * i];
     T bf[KS];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const T *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
-        bf[ks] = cb[lane_off + (unsigned)clamp_row(row0)];
-    }
+    for (int ks = 0; ks < KS; ++ks) bf[ks] = kload(ks, clamp_row(row0));
 #pragma unroll
     for (int i = 0; i < SE; ++i) {
-        const int e = threadIdx.x + 256 * i;
+        const int e = threadIdx.x + NTH * i;
         S[(e / W) * SP + (e % W)] = (T)sv[i];
     }
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < kUpdateTiles; ++t) {
-        const int row = row0 + t * 64;
-        if (!FULL && wrow + t * 64 >= rows) break;   // wave-uniform
+        const int row = row0 + t * TR;
+        if (!FULL && wrow + t * TR >= rows) break;   // wave-uniform
         // no instruction: keeps the V_P reads of each tile in its tile (merged
-        // across the unrolled tiles they would hold 128 registers throughout)
+        // across the unrolled tiles they would hold many more registers)
         asm volatile("" ::: "memory");
         T nb[KS];
         if (t + 1 < kUpdateTiles) {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const T *cb = X + (size_t)pivot_col(4 * ks, IJ, b) * ld;
-                nb[ks] = cb[lane_off + (unsigned)clamp_row(row + 64)];
-            }
+            for (int ks = 0; ks < KS; ++ks) nb[ks] = kload(ks, clamp_row(row + TR));
         }
         typename Mfma<T>::acc acc[NT];
 #pragma unroll
         for (int q = 0; q < NT; ++q) acc[q] = typename Mfma<T>::acc{0, 0, 0, 0};
-        // fully unrolled (a rolled k-loop indexes bf[] at run time)
+        // fully unrolled (a rolled k-loop indexes bf[] at run time); at
+        // W = 128 the V_P operands of four k-steps at a time (32 reads) are
+        // kept apart, else all 256 of a tile are read ahead into registers
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const T *srow = S + (4 * ks + lane / 16) * SP + (lane % 16);
+            if constexpr (W == 128)
+                if (ks % 4 == 0 && ks > 0) asm volatile("" ::: "memory");
+            const T *srow = S + (4 * ks + lq) * SP + (lane % 16);
 #pragma unroll
             for (int q = 0; q < NT; ++q) acc[q] = mfma16x16x4(srow[q * 16], bf[ks], acc[q]);
         }
         if (FULL || row < rows) {
-            // element r of tile q is column q 16 + Mfma<T>::row(lane, r) of the
-            // block pair (a 16-column tile lies inside one block: 16 | b)
+            // element r of tile q is pivot position q 16 + Mfma<T>::row(lane, r)
+            // (a 16-position tile lies inside one block: 16 | b)
+            // a uniform base (the block, the tile's first column of this
+            // element) plus a 32-bit per-lane byte offset
+            const unsigned lane_st =
+                ((unsigned)Mfma<T>::row(lane, 0) * (unsigned)ld + (unsigned)row) * (unsigned)sizeof(T);
 #pragma unroll
             for (int q = 0; q < NT; ++q)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    if constexpr (sizeof(T) == 8) {
-                        T *cb = X + (size_t)pivot_col(q * 16 + 4 * r, IJ, b) * ld;
-                        cb[lane_off + (unsigned)row] = acc[q][r];
-                    } else {
-                        T *cb = X + (size_t)(pivot_col(q * 16, IJ, b) + Mfma<T>::row(lane, r)) * ld;
-                        cb[(unsigned)row] = acc[q][r];
-                    }
+                    const bool in_i = q * 16 < HB;
+                    const int c0 = (in_i ? q * 16 : q * 16 - HB) + Mfma<T>::row(0, r);   // uniform
+                    if (UNEVEN && c0 + Mfma<T>::row(lane, 0) >= (in_i ? d.y : d.w)) continue;
+                    char *cb = (char *)(X + (size_t)(in_i ? d.x : d.z) * ld) + (size_t)c0 * colb;
+                    *(T *)(cb + lane_st) = acc[q][r];
                 }
         }
         if (t + 1 < kUpdateTiles) {
@@ -811,17 +1283,13 @@ __device__ __forceinline__ void update_tiles(T *__restrict__ X, long ld, int row
     }
 }
 
-template <int W, class T>
-__global__ __launch_bounds__(256) void k_update(T *__restrict__ G, int m, long ldg,
-                                                T *__restrict__ V, int nv, long ldv, int b,
-                                                const int2 *__restrict__ piv,
-                                                const double *__restrict__ vpt,
-                                                const int *__restrict__ flag, int groups_g)
+template <int W, class T, bool UNEVEN>
+__device__ __forceinline__ void update_body(T *__restrict__ G, int m, long ldg, T *__restrict__ V,
+                                            int nv, long ldv, const int4 *__restrict__ piv,
+                                            const double *__restrict__ vpt,
+                                            const int *__restrict__ flag, int groups_g, T *S)
 {
-    // V_P row-major with a row pitch of W + 16 doubles: the four 16-lane row
-    // groups of a fragment read then cover all 64 LDS banks in two cycles
-    constexpr int SP = W + 16;
-    __shared__ T S[W * SP];
+    constexpr int GR = UpdateShape<W>::group_rows;
     const int pv = blockIdx.y;
     const bool is_v = (int)blockIdx.x >= groups_g;
     const int f = flag[pv];
@@ -829,39 +1297,78 @@ __global__ __launch_bounds__(256) void k_update(T *__restrict__ G, int m, long l
     T *X = is_v ? V : G;
     const long ld = is_v ? ldv : ldg;
     const int rows = is_v ? nv : m;
-    const int2 IJ = piv[pv];
+    const int4 d = piv[pv];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int group = is_v ? (int)blockIdx.x - groups_g : (int)blockIdx.x;
-    const int wrow = group * 64 * kUpdateTiles + wave * 16;   // first row of the wavefront
+    const int wrow = group * GR + wave * 16;   // first row of the wavefront
     const double *src = vpt + (size_t)pv * W * W;
-    if ((group + 1) * 64 * kUpdateTiles <= rows)   // the same for the whole workgroup
-        update_tiles<W, T, true>(X, ld, rows, wrow, lane, IJ, b, src, S);
+    if ((group + 1) * GR <= rows)   // the same for the whole workgroup
+        update_tiles<W, T, true, UNEVEN>(X, ld, rows, wrow, lane, d, src, S);
     else
-        update_tiles<W, T, false>(X, ld, rows, wrow, lane, IJ, b, src, S);
+        update_tiles<W, T, false, UNEVEN>(X, ld, rows, wrow, lane, d, src, S);
+}
+
+// V_P row-major with a row pitch of W + 16 elements: the four 16-lane row
+// groups of a fragment read then cover all 64 LDS banks in two cycles.
+template <int W, class T, bool UNEVEN>
+__global__ __launch_bounds__(256) void k_update(T *__restrict__ G, int m, long ldg,
+                                                T *__restrict__ V, int nv, long ldv,
+                                                const int4 *__restrict__ piv,
+                                                const double *__restrict__ vpt,
+                                                const int *__restrict__ flag, int groups_g)
+{
+    static_assert(W <= 64, "256 threads");
+    __shared__ T S[W * (W + 16)];
+    update_body<W, T, UNEVEN>(G, m, ldg, V, nv, ldv, piv, vpt, flag, groups_g, S);
+}
+
+template <class T, bool UNEVEN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_update128(T *__restrict__ G, int m, long ldg,
+                                                   T *__restrict__ V, int nv, long ldv,
+                                                   const int4 *__restrict__ piv,
+                                                   const double *__restrict__ vpt,
+                                                   const int *__restrict__ flag, int groups_g)
+{
+    __shared__ T S[128 * (128 + 16)];
+    update_body<128, T, UNEVEN>(G, m, ldg, V, nv, ldv, piv, vpt, flag, groups_g, S);
 }
 
 // ------------------------------------------------------------ host driver
-bool block_width_supported(int b) { return b == 16 || b == 32; }
+bool block_width_supported(int b) { return b == 16 || b == 32 || b == 64; }
+
+// Blocks of the uniform partition (Sec. 3): N = 2 ceil(n / 2b) blocks,
+// widths n / N or n / N + 1 (the first n mod N blocks are the wider ones),
+// all at most b; every block needs a column.
+static int block_count(int n, int b) { return 2 * ((n + 2 * b - 1) / (2 * b)); }
 
 bool block_shape_supported(int m, int n, int b)
 {
-    return block_width_supported(b) && n % (2 * b) == 0 && m >= n;
+    return block_width_supported(b) && n >= 2 && m >= n && block_count(n, b) <= n;
 }
+
+bool block_partition_even(int n, int b) { return n % (2 * b) == 0; }
 
 int choose_block_width(int m, int n)
 {
-    (void)m;
-    if (n % 64 == 0) return 32;
-    if (n % 32 == 0) return 16;
-    return 32;   // rejected later by block_shape_supported
+    // the autotuner's choice when it has measured this shape, else the
+    // widest block whose pivot still leaves every step a few hundred
+    // workgroups of Gram and update work
+    int b = tuned_block_width(m, n);
+    if (b > 0) return b;
+    if (n >= 4096) return 64;
+    if (n >= 512) return 32;
+    return 16;
 }
 
 int auto_variant(int m, int n)
 {
-    (void)m;
-    (void)n;
-    return JEVD_VAR_POINTWISE;
+    const int v = tuned_variant(m, n);
+    if (v >= 0) return v;
+    // the block path wins once the matrix no longer fits the caches that
+    // make the pointwise steps cheap (measured on the MI355X: n = 1024 runs
+    // faster pointwise, n = 2048 and above block-oriented)
+    return n >= 2048 ? JEVD_VAR_BLOCK_ORIENTED : JEVD_VAR_POINTWISE;
 }
 
 namespace {
@@ -890,9 +1397,9 @@ int grow(T **p, size_t *cap, size_t need)
 }  // namespace
 
 struct BlockTables {
-    int b = -1, N = -1;
+    int b = -1, n = -1;
     std::vector<int> outer_start;   // host copy of the block ordering's step offsets
-    int2 *d_outer = nullptr;        // block pairs of every step (ring order)
+    int4 *d_outer = nullptr;        // pivots of every step (ring order): column ranges
     size_t cap_outer = 0;
 };
 
@@ -902,18 +1409,26 @@ static BlockTables *tables_of(BlockWorkspace *ws)
     return (BlockTables *)ws->tables;
 }
 
-static int prepare_tables(BlockWorkspace *ws, int N, int b, hipStream_t st)
+static int prepare_tables(BlockWorkspace *ws, int n, int b, hipStream_t st)
 {
     BlockTables *t = tables_of(ws);
-    if (t->N == N && t->b == b) return JEVD_OK;
-    std::vector<int> os, op;
+    if (t->n == n && t->b == b) return JEVD_OK;
+    const int N = block_count(n, b);
+    std::vector<int> os, op, bstart(N + 1, 0);
+    for (int k = 0; k < N; ++k) bstart[k + 1] = bstart[k] + n / N + (k < n % N ? 1 : 0);
     build_ordering(N, kOrdModModulus, os, op);
-    int rc = grow(&t->d_outer, &t->cap_outer, op.size() / 2 + 1);
+    std::vector<int4> desc(op.size() / 2);
+    for (size_t e = 0; e < desc.size(); ++e) {
+        const int I = op[2 * e], J = op[2 * e + 1];
+        desc[e] = make_int4(bstart[I], bstart[I + 1] - bstart[I], bstart[J], bstart[J + 1] - bstart[J]);
+    }
+    int rc = grow(&t->d_outer, &t->cap_outer, desc.size() + 1);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(t->d_outer, op.data(), op.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(t->d_outer, desc.data(), desc.size() * sizeof(int4),
+                           hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
     t->outer_start = os;
-    t->N = N;
+    t->n = n;
     t->b = b;
     return JEVD_OK;
 }
@@ -921,6 +1436,13 @@ static int prepare_tables(BlockWorkspace *ws, int N, int b, hipStream_t st)
 static size_t pivot_lds_bytes(int W)
 {
     return (2 * (size_t)W * (W + 1) + 3 * (size_t)(kPivotThreads / 64) * (W / 2)) * sizeof(double);
+}
+
+// Entries of the inner-transform log of one pivot (W = 128): one per pair
+// of every inner step of every inner sweep it may run.
+static long log_entries(int W, bool full_block, int max_inner)
+{
+    return (long)(full_block ? max_inner : 1) * W * (W / 2);
 }
 
 // One outer step: Gram, pivot solve, update of G and V (one launch each) on
@@ -933,13 +1455,16 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
                               int nsplit, int rows_per_split, SweepCounters *ctr, T *G, long ldg,
                               T *V, long ldv, double tol)
 {
-    const int npiv = t->N / 2;
-    const int2 *piv = t->d_outer + t->outer_start[k];
+    const int npiv = block_count(a.n, a.b) / 2;
+    const int4 *piv = t->d_outer + t->outer_start[k];
+    const bool uneven = !block_partition_even(a.n, a.b);
     hipStream_t st = a.stream;
     hipError_t e;
     if ((e = a.timer->begin(st, JEVD_K_GRAM)) != hipSuccess) return e;
-    k_gram<W, T><<<dim3(npiv, nsplit), 256, 0, st>>>(G, a.m, ldg, a.b, piv, rows_per_split,
-                                                      ws->partial);
+    if constexpr (W == 128)
+        k_gram128<T><<<dim3(npiv, nsplit), 256, 0, st>>>(G, a.m, ldg, piv, rows_per_split, ws->partial);
+    else
+        k_gram<W, T><<<dim3(npiv, nsplit), 256, 0, st>>>(G, a.m, ldg, piv, rows_per_split, ws->partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = a.timer->end(st)) != hipSuccess) return e;
 
@@ -960,31 +1485,51 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     p.m = a.m;
     p.ldg = ldg;
     p.sign_pivot = a.sign_pivot ? 1 : 0;
+    p.vlog = ws->vlog;
+    p.log_stride = log_entries(W, a.full_block, a.max_inner);
     if ((e = a.timer->begin(st, JEVD_K_PIVOT_SOLVE)) != hipSuccess) return e;
-    k_pivot_solve<W><<<npiv, kPivotThreads, pivot_lds_bytes(W), st>>>(p);
+    if constexpr (W == 128)
+        k_pivot_solve_log<128><<<npiv, kLogThreads, 0, st>>>(p);
+    else
+        k_pivot_solve<W><<<npiv, kPivotThreads, pivot_lds_bytes(W), st>>>(p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = a.timer->end(st)) != hipSuccess) return e;
 
-    const int rows_per_group = 64 * kUpdateTiles;
-    const int groups_g = (a.m + rows_per_group - 1) / rows_per_group;
-    const int groups_v = V ? (a.n + rows_per_group - 1) / rows_per_group : 0;
+    constexpr int GR = UpdateShape<W>::group_rows;
+    const int groups_g = (a.m + GR - 1) / GR;
+    const int groups_v = V ? (a.n + GR - 1) / GR : 0;
+    const dim3 grid(groups_g + groups_v, npiv);
     if ((e = a.timer->begin(st, JEVD_K_UPDATE)) != hipSuccess) return e;
-    k_update<W, T><<<dim3(groups_g + groups_v, npiv), 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, a.b,
-                                                                    piv, ws->vp, ws->flags,
-                                                                    groups_g);
+    if constexpr (W == 128) {
+        if (uneven)
+            k_update128<T, true><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, ws->vp,
+                                                       ws->flags, groups_g);
+        else
+            k_update128<T, false><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, ws->vp,
+                                                        ws->flags, groups_g);
+    } else {
+        if (uneven)
+            k_update<W, T, true><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, ws->vp,
+                                                       ws->flags, groups_g);
+        else
+            k_update<W, T, false><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, ws->vp,
+                                                        ws->flags, groups_g);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     return a.timer->end(st);
 }
 
-// Row split of the pivot Grams (about 1024 workgroups per step) and the
-// step workspaces; sets the pivot solve's LDS limit.
+// Row split of the pivot Grams (about 1024 workgroups per step for W <= 64,
+// 512 for W = 128, whose workgroups are twice as long) and the step
+// workspaces; sets the pivot solve's LDS limit.
 static int prepare_steps(BlockWorkspace *ws, const BlockRunArgs &a, int *nsplit_out,
                          int *rows_per_split_out)
 {
-    const int b = a.b, W = 2 * b, N = a.n / b, npiv = N / 2;
-    int rc = prepare_tables(ws, N, b, a.stream);
+    const int b = a.b, W = 2 * b, npiv = block_count(a.n, b) / 2;
+    int rc = prepare_tables(ws, a.n, b, a.stream);
     if (rc) return rc;
-    int nsplit = 1024 / npiv;
+    const int target = (W == 128) ? 512 : 1024;
+    int nsplit = target / npiv;
     if (nsplit < 1) nsplit = 1;
     int maxsplit = (a.m + 255) / 256;
     if (nsplit > maxsplit) nsplit = maxsplit;
@@ -997,6 +1542,10 @@ static int prepare_steps(BlockWorkspace *ws, const BlockRunArgs &a, int *nsplit_
     if (rc) return rc;
     rc = grow(&ws->flags, &ws->capFlags, (size_t)npiv);
     if (rc) return rc;
+    if (W == 128) {
+        rc = grow(&ws->vlog, &ws->capVlog, (size_t)npiv * log_entries(W, a.full_block, a.max_inner));
+        if (rc) return rc;
+    }
     if (W == 64)
         HIP_TRY(hipFuncSetAttribute((const void *)k_pivot_solve<64>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1021,13 +1570,17 @@ static int block_sweeps(BlockWorkspace *ws, const BlockRunArgs &a, T *G, long ld
     int rc = prepare_steps(ws, a, &nsplit, &rows_per_split);
     if (rc) return rc;
     BlockTables *t = tables_of(ws);
-    const int N = a.n / a.b;
+    const int N = block_count(a.n, a.b);
     HIP_TRY(hipMemsetAsync(dctr, 0, sizeof(SweepCounters) * max_sweeps, a.stream));
     for (int s = 0; s < max_sweeps; ++s) {
         for (int k = 0; k < N; ++k) {
-            hipError_t e = (a.b == 16)
-                ? launch_step<32, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol)
-                : launch_step<64, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol);
+            hipError_t e;
+            if (a.b == 16)
+                e = launch_step<32, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol);
+            else if (a.b == 32)
+                e = launch_step<64, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol);
+            else
+                e = launch_step<128, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol);
             HIP_TRY(e);
         }
         HIP_TRY(hipMemcpyAsync(hctr + s, dctr + s, sizeof(SweepCounters), hipMemcpyDeviceToHost,
@@ -1042,10 +1595,20 @@ static int block_sweeps(BlockWorkspace *ws, const BlockRunArgs &a, T *G, long ld
     return JEVD_ENOCONV;
 }
 
+// Sign pivoting moves columns between pivot positions, so empty positions
+// (uneven partitions) and the W = 128 pivot solve (unpivoted only) are
+// excluded.
+bool block_options_supported(int m, int n, int b, bool sign_pivot)
+{
+    if (!block_shape_supported(m, n, b)) return false;
+    if (sign_pivot && (b == 64 || !block_partition_even(n, b))) return false;
+    return true;
+}
+
 int run_block(BlockWorkspace *ws, const BlockRunArgs &a, int *sweeps_done)
 {
     *sweeps_done = 0;
-    if (!block_shape_supported(a.m, a.n, a.b)) return JEVD_EINVAL;
+    if (!block_options_supported(a.m, a.n, a.b, a.sign_pivot)) return JEVD_EINVAL;
     return block_sweeps<double>(ws, a, a.G, a.ldg, a.V, a.ldv, a.tol, a.max_sweeps, a.dctr, a.hctr,
                                 sweeps_done);
 }
@@ -1109,7 +1672,7 @@ int run_block_mixed(BlockWorkspace *ws, const BlockRunArgs &a, int max_sweeps_lo
 {
     *sweeps_low = 0;
     *sweeps_done = 0;
-    if (!block_shape_supported(a.m, a.n, a.b) || !a.V) return JEVD_EINVAL;
+    if (!block_options_supported(a.m, a.n, a.b, a.sign_pivot) || !a.V) return JEVD_EINVAL;
     const int m = a.m, n = a.n;
     hipStream_t st = a.stream;
     int rc;
@@ -1157,6 +1720,7 @@ void block_workspace_free(BlockWorkspace *ws)
     if (ws->partial) (void)hipFree(ws->partial);
     if (ws->vp) (void)hipFree(ws->vp);
     if (ws->flags) (void)hipFree(ws->flags);
+    if (ws->vlog) (void)hipFree(ws->vlog);
     if (ws->g32) (void)hipFree(ws->g32);
     if (ws->v32) (void)hipFree(ws->v32);
     if (ws->t64) (void)hipFree(ws->t64);

@@ -21,7 +21,8 @@ INFO_MAX_SWEEPS = 64
 EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "jevd_validate",
            "jevd_get_info", "jevd_set_timing", "jevd_strerror", "jevd_ordering",
            "jevd_batch_create", "jevd_batch_run", "jevd_batch_results", "jevd_batch_destroy",
-           "jacobi_evd_batched", "jevd_canonicalize", "jevd_adjoint")
+           "jacobi_evd_batched", "jevd_canonicalize", "jevd_adjoint", "jevd_autotune",
+           "jevd_tune_file", "jevd_tune_lookup", "jevd_tune_record")
 K_PAIR_STEP, K_GRAM, K_PIVOT_SOLVE, K_UPDATE = 0, 1, 2, 3
 
 
@@ -84,6 +85,12 @@ def lib():
                                         _vp, _vp, _vp]
         L.jevd_adjoint.argtypes = [_vp, _i, _i, _i, _vp, _i, _ll, _vp, _ll, _vp, _ll, _vp, _i, _ll,
                                    _vp, _ll, _vp, _i, _ll, _vp, _i, _ll]
+        _dp = ctypes.POINTER(ctypes.c_double)
+        L.jevd_autotune.argtypes = [_vp, _i, _i, _vp, _i, _vp, ctypes.c_double,
+                                    ctypes.POINTER(jevd_opts), _i, _ip, _ip, _dp]
+        L.jevd_tune_file.argtypes = [ctypes.c_char_p]
+        L.jevd_tune_lookup.argtypes = [_i, _i, _ip, _ip, _dp]
+        L.jevd_tune_record.argtypes = [_i, _i, _i, _i, ctypes.c_double]
         for name in EXPORTS:
             if name != "jevd_strerror":
                 getattr(L, name).restype = ctypes.c_int
@@ -126,6 +133,35 @@ def jacobi_evd(h, m, n, G_ptr, ldg, J_host, tol, opts, lambda_ptr, U_ptr, ldu, V
                           _vp(lambda_ptr) if lambda_ptr else None, _vp(U_ptr) if U_ptr else None,
                           ldu, _vp(V_ptr) if V_ptr else None, ldv, ctypes.byref(sweeps))
     return st, sweeps.value
+
+
+def jevd_autotune(h, m, n, G_ptr, ldg, J_host, tol, opts, want_v):
+    """Measures the candidate configurations on a copy of the device matrix
+    at G_ptr and records the fastest.  Returns (status, block, variant, ms)."""
+    Jbuf = None
+    if J_host is not None:
+        Jbuf = (ctypes.c_byte * n).from_buffer_copy(bytes(J_host))
+    b, v, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    st = lib().jevd_autotune(h, m, n, _vp(G_ptr), ldg,
+                             ctypes.cast(Jbuf, _vp) if Jbuf is not None else None, float(tol),
+                             ctypes.byref(opts) if opts is not None else None, 1 if want_v else 0,
+                             ctypes.byref(b), ctypes.byref(v), ctypes.byref(ms))
+    return st, b.value, v.value, ms.value
+
+
+def jevd_tune_file(path):
+    return lib().jevd_tune_file(None if path is None else os.fsencode(path))
+
+
+def jevd_tune_lookup(m, n):
+    """Returns (status, block, variant, ms) of the tune table's record."""
+    b, v, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_double(0.0)
+    st = lib().jevd_tune_lookup(m, n, ctypes.byref(b), ctypes.byref(v), ctypes.byref(ms))
+    return st, b.value, v.value, ms.value
+
+
+def jevd_tune_record(m, n, block, variant, ms):
+    return lib().jevd_tune_record(m, n, block, variant, float(ms))
 
 
 def jevd_validate(m, n, ldg, J_host, tol, opts, has_U, ldu, has_V, ldv):

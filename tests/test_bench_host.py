@@ -58,3 +58,41 @@ def test_committed_traffic_records_name_existing_sources_and_known_workloads():
             assert os.path.exists(os.path.join(ROOT, f)), (kernel, f)
         assert '"%s"' % rec["workload"] in bench_text, (kernel, rec["workload"])
         assert rec["fetch_kib_per_launch"] > 0 and rec["write_kib_per_launch"] > 0
+
+
+def test_golden_lookup_requires_the_same_input_bytes(tmp_path):
+    """The benchmark's eigenvalue gate for the large block inputs uses the
+    cached oracle solve only for the exact input bytes it was computed on."""
+    import numpy as np
+    from paper_1008_0201_amd import workloads as W
+    B = load_bench()
+    G = np.asfortranarray(np.arange(12.0).reshape(4, 3) + 0.5)
+    (tmp_path / "x.json").write_text(json.dumps({"input_sha256": W.input_sha256(G), "oracle": "o",
+                                                 "sweeps": 3}))
+    np.save(tmp_path / "x.lam.npy", np.array([1.0, 2.0, 3.0]))
+    B.GOLDEN = str(tmp_path)
+    B.GOLDEN_OF = {"wl": "x"}
+    lam, meta = B.golden_eigs("wl", G)
+    assert list(lam) == [1.0, 2.0, 3.0] and meta["sweeps"] == 3
+    G2 = G.copy()
+    G2[1, 2] = np.nextafter(G2[1, 2], 1e9)
+    lam2, why = B.golden_eigs("wl", G2)
+    assert lam2 is None and "differ" in why["reason"]
+    assert B.golden_eigs("other", G)[0] is None
+
+
+def test_committed_golden_records_are_complete():
+    """Each cached oracle solve under tests/golden/ has its eigenvalues, the
+    input hash, the oracle configuration and the command that made it."""
+    import glob
+    import numpy as np
+    B = load_bench()
+    names = set(B.GOLDEN_OF.values())
+    for path in glob.glob(os.path.join(ROOT, "tests", "golden", "*.json")):
+        meta = json.load(open(path))
+        name = os.path.basename(path)[:-len(".json")]
+        assert name in names, name
+        lam = np.load(path[:-len(".json")] + ".lam.npy", allow_pickle=False)
+        assert lam.shape == (meta["n"],) and np.all(np.isfinite(lam))
+        assert len(meta["input_sha256"]) == 64 and meta["status"] == 0
+        assert meta["command"].startswith("python tests/golden/make_block_golden.py")

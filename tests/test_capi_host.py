@@ -157,3 +157,82 @@ def test_opts_struct_matches_header():
     J = bytes([1] * 63 + [255])
     assert B.jevd_validate(64, 64, 64, J, 0.0, o, False, 64, False, 64) == B.JEVD_EINVAL
     assert B.jevd_validate(64, 64, 64, None, 0.0, o, False, 64, False, 64) == B.JEVD_OK
+
+
+@pytest.mark.parametrize("m,n,variant,block,pivot,ok", [
+    (256, 256, 1, 16, 0, True), (256, 256, 1, 32, 0, True), (256, 256, 1, 64, 0, True),
+    (256, 256, 2, 64, 0, True),
+    (256, 256, 1, 64, 1, False),        # b = 64 runs the unpivoted pivot solve only
+    (256, 256, 2, 32, 1, True),         # sign pivoting at b <= 32
+    (1000, 1000, 1, 32, 0, True),       # uneven partition: 32 blocks of 31 or 32 columns
+    (1030, 1030, 2, 64, 0, True),       # 18 blocks of 57 or 58 columns
+    (1000, 1000, 1, 32, 1, False),      # sign pivoting needs n divisible by 2b
+    (70, 70, 1, 32, 0, True),           # 4 blocks of 17 or 18 columns (each <= b)
+    (3, 3, 1, 16, 0, True), (2, 2, 2, 16, 0, True),
+    (1, 1, 1, 16, 0, False),            # a block pivot needs two columns
+    (1000, 1000, 1, 24, 0, False), (1000, 1000, 1, 128, 0, False),   # unsupported widths
+])
+def test_block_options_as_documented(m, n, variant, block, pivot, ok):
+    """Each value the header documents for opts.block / opts.pivot with the
+    block variants is accepted or rejected as documented (Sec. 3: widths of
+    the uniform partition differ by at most one)."""
+    o = B.jevd_default_opts()
+    o.variant, o.block, o.pivot = variant, block, pivot
+    st = B.jevd_validate(m, n, m, None, 0.0, o, False, m, False, n)
+    assert (st == B.JEVD_OK) == ok, st
+
+
+def test_tune_table_record_lookup_and_file(tmp_path):
+    """The autotuner's table: records persist in the tune file, the last
+    record of a shape wins, invalid records are refused, and block = 0
+    follows the record (here: b = 64 for 256 x 256, which then refuses sign
+    pivoting)."""
+    path = str(tmp_path / "tune.txt")
+    assert B.jevd_tune_file(path) == B.JEVD_OK
+    try:
+        assert B.jevd_tune_lookup(256, 256)[0] == B.JEVD_EINVAL
+        assert B.jevd_tune_record(256, 256, 32, B.VAR_FULL_BLOCK, 12.5) == B.JEVD_OK
+        assert B.jevd_tune_record(256, 256, 64, B.VAR_BLOCK_ORIENTED, 10.0) == B.JEVD_OK
+        assert B.jevd_tune_record(1024, 1024, 0, B.VAR_POINTWISE, 60.0) == B.JEVD_OK
+        assert B.jevd_tune_record(256, 256, 24, B.VAR_BLOCK_ORIENTED, 1.0) == B.JEVD_EINVAL
+        assert B.jevd_tune_record(256, 256, 32, B.VAR_POINTWISE, 1.0) == B.JEVD_EINVAL
+        assert B.jevd_tune_record(256, 256, 32, B.VAR_AUTO, 1.0) == B.JEVD_EINVAL
+        assert B.jevd_tune_record(256, 256, 32, B.VAR_BLOCK_ORIENTED, -1.0) == B.JEVD_EINVAL
+        assert B.jevd_tune_lookup(256, 256) == (B.JEVD_OK, 64, B.VAR_BLOCK_ORIENTED, 10.0)
+        lines = open(path).read().split("\n")
+        assert "256 256 64 1 10.000000" in lines and "1024 1024 0 0 60.000000" in lines
+        # a fresh load of the file gives the same table
+        assert B.jevd_tune_file(path) == B.JEVD_OK
+        assert B.jevd_tune_lookup(256, 256) == (B.JEVD_OK, 64, B.VAR_BLOCK_ORIENTED, 10.0)
+        assert B.jevd_tune_lookup(1024, 1024) == (B.JEVD_OK, 0, B.VAR_POINTWISE, 60.0)
+        o = B.jevd_default_opts()          # variant AUTO, block 0
+        assert B.jevd_validate(256, 256, 256, None, 0.0, o, False, 256, False, 256) == B.JEVD_OK
+        # block 0 takes the recorded b = 64, which has no sign pivoting
+        o.variant, o.pivot = B.VAR_BLOCK_ORIENTED, B.PIVOT_SIGN
+        assert B.jevd_validate(256, 256, 256, None, 0.0, o, False, 256, False, 256) == B.JEVD_EINVAL
+        o.block = 32
+        assert B.jevd_validate(256, 256, 256, None, 0.0, o, False, 256, False, 256) == B.JEVD_OK
+        # an unreadable line is skipped, the rest is kept
+        with open(path, "a") as f:
+            f.write("garbage line\n512 512 32 2 3.5\n")
+        assert B.jevd_tune_file(path) == B.JEVD_OK
+        assert B.jevd_tune_lookup(512, 512) == (B.JEVD_OK, 32, B.VAR_FULL_BLOCK, 3.5)
+    finally:
+        B.jevd_tune_file(str(tmp_path / "empty.txt"))
+
+
+def test_auto_variant_untuned_shapes(tmp_path):
+    """Without a record, JEVD_VAR_AUTO is pointwise below n = 2048 (any n
+    then validates) and block-oriented from n = 2048 (the block partition
+    rules apply: sign pivoting is refused for a width that does not divide
+    n evenly)."""
+    B.jevd_tune_file(str(tmp_path / "none.txt"))
+    o = B.jevd_default_opts()
+    assert B.jevd_validate(1999, 1999, 1999, None, 0.0, o, False, 1999, False, 1999) == B.JEVD_OK
+    o.pivot = B.PIVOT_SIGN
+    # pointwise has no Cholesky: sign pivoting needs an explicit block variant
+    assert B.jevd_validate(2048, 2048, 2048, None, 0.0, o, False, 2048, False, 2048) == B.JEVD_EINVAL
+    o.variant = B.VAR_BLOCK_ORIENTED
+    assert B.jevd_validate(2050, 2050, 2050, None, 0.0, o, False, 2050, False, 2050) == B.JEVD_EINVAL
+    o.pivot = B.PIVOT_NONE
+    assert B.jevd_validate(2050, 2050, 2050, None, 0.0, o, False, 2050, False, 2050) == B.JEVD_OK

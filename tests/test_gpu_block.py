@@ -58,7 +58,7 @@ def check_eigs(orc, G, J, lam_gpu, lam_ref):
 
 
 def check(orc, G, J, tol, b, full_block, got):
-    ref = orc.block_jevd(G, J, tol, b=b, full_block=full_block, want_v=True)
+    ref = orc.block_jevd(G, J, tol, b=b, full_block=full_block, want_v=True, nthreads=0)
     assert ref.status == 0 and got["st"] == 0, (ref.status, got["st"])
     check_eigs(orc, G, J, got["lam"], ref.lam)
     assert abs(got["sweeps"] - ref.sweeps) <= 1, (got["sweeps"], ref.sweeps)
@@ -84,7 +84,7 @@ def check(orc, G, J, tol, b, full_block, got):
 
 
 @pytest.mark.parametrize("n,m,b", [(64, 64, 16), (128, 128, 32), (128, 200, 16), (256, 256, 32),
-                                   (320, 333, 32)])
+                                   (320, 333, 32), (256, 256, 64), (384, 400, 64)])
 @pytest.mark.parametrize("full_block", [False, True])
 def test_block_trig_row_graded(solver, orc, n, m, b, full_block):
     """J = I, row-graded factor (the block workload's recipe at small size)."""
@@ -94,7 +94,7 @@ def test_block_trig_row_graded(solver, orc, n, m, b, full_block):
     print("n=%d b=%d fb=%d sweeps gpu %d oracle %d" % (n, b, full_block, got["sweeps"], ref.sweeps))
 
 
-@pytest.mark.parametrize("n,b", [(128, 16), (256, 32)])
+@pytest.mark.parametrize("n,b", [(128, 16), (256, 32), (512, 64)])
 @pytest.mark.parametrize("full_block", [False, True])
 def test_block_hyperbolic(solver, orc, n, b, full_block):
     """Block hyperbolic with unpivoted Cholesky (Alg. 3.4, HB / HF)."""
@@ -124,8 +124,9 @@ def test_block_workload_recipe_small(solver, orc):
     print("n=1024 block workload recipe: sweeps gpu %d oracle %d" % (got["sweeps"], ref.sweeps))
 
 
+@pytest.mark.parametrize("b", [32, 64])
 @pytest.mark.parametrize("full_block", [False, True])
-def test_block_cholesky_breakdown_path(solver, orc, full_block):
+def test_block_cholesky_breakdown_path(solver, orc, full_block, b):
     """A zero column gives a pivot Gram a zero diagonal entry, so its Cholesky
     factorisation breaks down on both sides (deterministically); that pivot
     is then processed on the columns of G_P itself, with V_P still
@@ -133,13 +134,13 @@ def test_block_cholesky_breakdown_path(solver, orc, full_block):
     n = 128
     G = W.graded_rows(n + 8, n, k=77, decades=2.0, cond_decades=2.0)
     G[:, 37] = 0.0
-    got = run(solver, G, None, n * EPS, 2 if full_block else 1, 32)
-    ref = orc.block_jevd(G, None, n * EPS, b=32, full_block=full_block, want_v=True)
+    got = run(solver, G, None, n * EPS, 2 if full_block else 1, b)
+    ref = orc.block_jevd(G, None, n * EPS, b=b, full_block=full_block, want_v=True)
     assert ref.extra > 0 and got["info"].breakdowns > 0
     assert ref.status == 0 and got["st"] == 0
     assert got["lam"][37] == 0.0 and np.all(got["U"][:, 37] == 0.0)
     nz = np.arange(n) != 37
-    assert rel_err(got["lam"][nz], ref.lam[nz]) <= REL_TOL
+    check_eigs(orc, G[:, nz], None, got["lam"][nz], ref.lam[nz])
     V = got["V"]
     assert np.max(np.abs(V.T @ V - np.eye(n))) <= max(10 * n * EPS, 4 * np.max(np.abs(ref.V.T @ ref.V - np.eye(n))))
     GV = (G.astype(np.longdouble) @ V.astype(np.longdouble)).astype(np.float64)
@@ -156,3 +157,30 @@ def test_block_status_paths(solver, orc):
     G2[3, 70] = np.inf
     got = run(solver, G2, None, 0.0, 1, 32)
     assert got["st"] == -2
+
+
+@pytest.mark.parametrize("n,b,full_block", [(1000, 32, False), (1030, 64, False), (1030, 64, True),
+                                            (1000, 16, True)])
+def test_block_uneven_partition(solver, orc, n, b, full_block):
+    """n not divisible by 2b: N = 2 ceil(n / 2b) blocks whose widths differ by
+    at most one (Sec. 3), e.g. 32 blocks of 31 or 32 columns for n = 1000,
+    b = 32, and 18 blocks of 57 or 58 for n = 1030, b = 64.  The GPU pads
+    each block to b positions (empty ones carry identity rows of the pivot
+    Gram and transform); the oracle works on the exact widths, so the inner
+    orders differ and the results agree to the eigenvalue gate, not bit for
+    bit."""
+    wl = W.graded_spd_transposed(n, k=2, lam_decades=3.0)
+    got = run(solver, wl.G, None, wl.tol, 2 if full_block else 1, b)
+    ref = check(orc, wl.G, None, wl.tol, b, full_block, got)
+    print("n=%d b=%d fb=%d uneven: sweeps gpu %d oracle %d" % (n, b, full_block, got["sweeps"],
+                                                               ref.sweeps))
+
+
+@pytest.mark.parametrize("n,m,b,full_block", [(300, 300, 32, False), (300, 317, 32, True),
+                                              (70, 70, 32, False), (200, 200, 64, True)])
+def test_block_uneven_hyperbolic(solver, orc, n, m, b, full_block):
+    """Ragged block partitions on indefinite inputs, including blocks far
+    narrower than b (n = 70, b = 32: four blocks of 17 or 18 columns)."""
+    wl = W.graded_hyperbolic(n, k=450 + n, grade=2.0, m=m)
+    got = run(solver, wl.G, wl.J, wl.tol, 2 if full_block else 1, b)
+    check(orc, wl.G, wl.J, wl.tol, b, full_block, got)
