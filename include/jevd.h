@@ -292,6 +292,26 @@ int jevd_tune_file(const char *path);
 int jevd_tune_lookup(int m, int n, int *block, int *variant, double *ms);
 int jevd_tune_record(int m, int n, int block, int variant, double ms);
 
+/*
+ * jevd_adjoint_noalloc: jevd_adjoint for callers that cannot allocate (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and results as jevd_adjoint, but the work arrays
+ * (3 n^2 + m n doubles per instance) live in a fixed 32 MiB device array of
+ * the library (4194304 doubles; one copy per GPU, set up by jevd_create and
+ * held until the process ends) instead of the handle's workspace, so the
+ * call never allocates.  Returns JEVD_EINVAL, before any device work, when
+ * batch * (3 n^2 + m n) exceeds 4194304 doubles, and for the argument errors
+ * of jevd_adjoint.  All calls on one GPU share the array: calls that overlap
+ * in time on one GPU (other streams, other threads) race and give wrong
+ * results; calls ordered on one stream are safe.  Only enqueues work on the
+ * handle's stream.
+ */
+int jevd_adjoint_noalloc(jevd_handle_t h, int batch, int m, int n, const double *G, int ldg,
+                         long long sg, const signed char *J, long long sj, const double *lam,
+                         long long slam, const double *U, int ldu, long long su, const double *w,
+                         long long sw, const double *C, int ldc, long long sc, double *dG, int ldd,
+                         long long sd);
+
 /* Host-only argument check that jacobi_evd runs before any device work
  * (same rules; G, lambda and the handle are not examined).  Returns JEVD_OK
  * or JEVD_EINVAL.  No device work. */

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -46,9 +47,40 @@ struct jevd_batch_s {
     bool ran = false;
 };
 
+// Work memory of jevd_adjoint_noalloc: a fixed array in the library's code
+// object, one copy per GPU, held until the process ends.  Host code never
+// uses the name itself (a host-side stand-in, not a device address): the
+// device address is looked up once per device (scratch_address) and passed
+// to the kernels like any workspace.
+constexpr size_t kScratchDoubles = (size_t)4 << 20;   // 32 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[64] = {};   // per device ordinal
+
+// The device address of `scratch` on the current device (dev), looked up
+// with that device current on first use; nullptr if the lookup fails.
+double *scratch_address(int dev)
+{
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
 struct jevd_handle_s {
     int device = 0;
     hipStream_t stream = nullptr;
+    double *scratch = nullptr;   // this device's `scratch` (jevd_adjoint_noalloc)
 
     signed char *dJ = nullptr;
     size_t capJ = 0;
@@ -253,6 +285,11 @@ int jevd_create(jevd_handle_t *h, void *stream)
     if (!p) return JEVD_ENOMEM;
     p->device = dev;
     p->stream = (hipStream_t)stream;
+    p->scratch = scratch_address(dev);
+    if (!p->scratch) {
+        jevd_destroy(p);
+        return JEVD_EHIP;
+    }
     std::memset(&p->info, 0, sizeof(p->info));
     if (hipHostMalloc((void **)&p->hsweeps, sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void **)&p->dsweeps, sizeof(int)) != hipSuccess) {
@@ -618,6 +655,32 @@ int jevd_adjoint(jevd_handle_t h, int batch, int m, int n, const double *G, int 
     if ((st = grow_device(&h->adjT, &h->capAdjT, mn))) return st;
     HIP_TRY(launch_adjoint(batch, m, n, G, ldg, sg, J, sj, lam, slam, U, ldu, su, w, sw, C, ldc, sc,
                            dG, ldd, sd, h->adjK, h->adjW, h->adjM, h->adjT, h->stream));
+    return JEVD_OK;
+}
+
+// jevd_adjoint on the library's fixed scratch array instead of the
+// handle's work arrays: no allocation at all (for callers that cannot
+// allocate).  The kernels and arguments are those of jevd_adjoint; every
+// work array is fully written before it is read, so nothing needs clearing.
+int jevd_adjoint_noalloc(jevd_handle_t h, int batch, int m, int n, const double *G, int ldg,
+                         long long sg, const signed char *J, long long sj, const double *lam,
+                         long long slam, const double *U, int ldu, long long su, const double *w,
+                         long long sw, const double *C, int ldc, long long sc, double *dG, int ldd,
+                         long long sd)
+{
+    if (!h || batch < 1 || n < 1 || m < n || !G || !lam || !U || !dG) return JEVD_EINVAL;
+    if (ldg < m || ldu < m || ldd < m || slam < n) return JEVD_EINVAL;
+    if (sg < (long long)ldg * n || su < (long long)ldu * n || sd < (long long)ldd * n) return JEVD_EINVAL;
+    if (J && sj < n) return JEVD_EINVAL;
+    if (w && sw < n) return JEVD_EINVAL;
+    if (C && (ldc < m || sc < (long long)ldc * n)) return JEVD_EINVAL;
+    if (batch > 65535) return JEVD_EINVAL;
+    const size_t nn = (size_t)n * n * batch, mn = (size_t)m * n * batch;
+    if (3 * nn + mn > kScratchDoubles) return JEVD_EINVAL;   // beyond the fixed scratch
+    if (!h->scratch) return JEVD_EHIP;
+    double *K = h->scratch, *Wk = K + nn, *M = Wk + nn, *T = M + nn;
+    HIP_TRY(launch_adjoint(batch, m, n, G, ldg, sg, J, sj, lam, slam, U, ldu, su, w, sw, C, ldc, sc,
+                           dG, ldd, sd, K, Wk, M, T, h->stream));
     return JEVD_OK;
 }
 

@@ -21,7 +21,8 @@ INFO_MAX_SWEEPS = 64
 EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "jevd_validate",
            "jevd_get_info", "jevd_set_timing", "jevd_strerror", "jevd_ordering",
            "jevd_batch_create", "jevd_batch_run", "jevd_batch_results", "jevd_batch_destroy",
-           "jacobi_evd_batched", "jevd_canonicalize", "jevd_adjoint", "jevd_autotune",
+           "jacobi_evd_batched", "jevd_canonicalize", "jevd_adjoint", "jevd_adjoint_noalloc",
+           "jevd_autotune",
            "jevd_tune_file", "jevd_tune_lookup", "jevd_tune_record")
 K_PAIR_STEP, K_GRAM, K_PIVOT_SOLVE, K_UPDATE = 0, 1, 2, 3
 
@@ -85,6 +86,7 @@ def lib():
                                         _vp, _vp, _vp]
         L.jevd_adjoint.argtypes = [_vp, _i, _i, _i, _vp, _i, _ll, _vp, _ll, _vp, _ll, _vp, _i, _ll,
                                    _vp, _ll, _vp, _i, _ll, _vp, _i, _ll]
+        L.jevd_adjoint_noalloc.argtypes = L.jevd_adjoint.argtypes
         _dp = ctypes.POINTER(ctypes.c_double)
         L.jevd_autotune.argtypes = [_vp, _i, _i, _vp, _i, _vp, ctypes.c_double,
                                     ctypes.POINTER(jevd_opts), _i, _ip, _ip, _dp]
@@ -281,6 +283,14 @@ def jevd_adjoint(h, batch, m, n, G, ldg, sg, J, sj, lam, slam, U, ldu, su, w, sw
     device int8 array."""
     return lib().jevd_adjoint(h, batch, m, n, _p(G), ldg, sg, _p(J), sj, _p(lam), slam, _p(U), ldu,
                               su, _p(w), sw, _p(C), ldc, sc, _p(dG), ldd, sd)
+
+
+def jevd_adjoint_noalloc(h, batch, m, n, G, ldg, sg, J, sj, lam, slam, U, ldu, su, w, sw, C, ldc,
+                         sc, dG, ldd, sd):
+    """jevd_adjoint on the library's fixed scratch (no allocation); same
+    arguments."""
+    return lib().jevd_adjoint_noalloc(h, batch, m, n, _p(G), ldg, sg, _p(J), sj, _p(lam), slam, _p(U),
+                                      ldu, su, _p(w), sw, _p(C), ldc, sc, _p(dG), ldd, sd)
 
 
 # ----------------------------------------------------------- torch front end
