@@ -13,7 +13,8 @@ struct BlockWorkspace {
     double *vp = nullptr;       // per pivot W x W accumulated transform, row-major
     int *flags = nullptr;       // per pivot: 1 if its transform must be applied
     double2 *vlog = nullptr;    // W = 128: per pivot the log of its inner transforms
-    size_t capPartial = 0, capVp = 0, capFlags = 0, capVlog = 0;
+    double *ap = nullptr;       // per pivot the W x W Gram, added up over the splits
+    size_t capPartial = 0, capVp = 0, capFlags = 0, capVlog = 0, capAp = 0;
     void *tables = nullptr;     // block and inner orderings (device copies)
     // mixed precision: FP32 iterate and transform, FP64 work arrays
     float *g32 = nullptr, *v32 = nullptr;

@@ -81,6 +81,16 @@ __device__ __forceinline__ bool pivot_real(int k, int4 d, int b)
     return k < b ? k < d.y : (k - b) < d.w;
 }
 
+// Orders the LDS accesses of one wavefront across lanes: one wavefront's
+// LDS operations complete in issue order, and the fences keep the compiler
+// from moving them across this point.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ------------------------------------------------------------------ k_gram
 // Tile t of the upper triangle of NT x NT tiles, row-major: row and column.
 __host__ __device__ constexpr int upper_tile_i(int NT, int t)
@@ -278,6 +288,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     gram_body<128, T>(G, m, ldg, piv, rows_per_split, partial);
 }
 
+// ----------------------------------------------------------- k_gram_reduce
+// Adds the split-K partial Grams of every pivot in split order (the same
+// order for every entry, so the sum is deterministic) and writes the full
+// symmetric A_P (W x W, column-major) for the pivot solve.  The partials
+// hold the upper 16 x 16 tiles (diagonal tiles whole); an entry of a lower
+// tile is its transpose.  An empty pivot position (a block narrower than b)
+// has a zero row and column, and gets 1 on the diagonal: an identity row and
+// column of A_P.  Spread over the whole chip, so the pivot solve (one
+// workgroup per pivot) copies a finished matrix instead of waiting on nsplit
+// scattered loads per entry.
+template <int W>
+__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ partial,
+                                                     int nsplit, const int4 *__restrict__ piv,
+                                                     int b, double *__restrict__ ap)
+{
+    const int pv = blockIdx.y;
+    const int e = blockIdx.x * 256 + threadIdx.x;   // entry (r, c) of the upper storage
+    if (e >= W * W) return;
+    const int r = e % W, c = e / W;
+    if ((r / 16) > (c / 16) || ((r / 16) == (c / 16) && r > c)) return;   // lower: written below
+    const double *src = partial + (size_t)pv * nsplit * W * W + e;
+    double v[8];
+    double acc = 0.0;
+    for (int s0 = 0; s0 < nsplit; s0 += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = (s0 + u < nsplit) ? src[(size_t)(s0 + u) * W * W] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (s0 + u < nsplit) acc += v[u];
+    }
+    if (r == c && !pivot_real(r, piv[pv], b)) acc = 1.0;
+    double *out = ap + (size_t)pv * W * W;
+    out[(size_t)c * W + r] = acc;
+    out[(size_t)r * W + c] = acc;
+}
+
 // ---------------------------------------------------------- k_pivot_solve
 // Inner orderings over the W = 2b columns of a pivot, in closed form (no
 // table reads on the critical path of an inner step):
@@ -295,6 +341,21 @@ __device__ __forceinline__ int2 inner_pair(int all_pairs, int W, int s, int r)
     }
     const int b = W / 2;
     return make_int2(r, b + (r + s) % b);
+}
+
+// inner_pair with the ordering fixed at compile time (no branch on it in
+// the step loops).
+template <bool ALL>
+__device__ __forceinline__ int2 inner_pair_t(int W, int s, int r)
+{
+    if constexpr (ALL) {
+        int i, j;
+        modulus_pair(W, s + 1, r, &i, &j);
+        return make_int2(i, j);
+    } else {
+        const int b = W / 2;
+        return make_int2(r, b + (r + s) % b);
+    }
 }
 
 // Breakdown path: one inner sweep directly on the columns of G_P (len rows,
@@ -357,8 +418,7 @@ __device__ void inner_sweep_global(double *X, long ldx, int len, double *Y, long
 }
 
 struct PivotSolveArgs {
-    const double *partial;
-    int nsplit;
+    const double *ap;   // per pivot the W x W Gram A_P (column-major), from k_gram_reduce
     signed char *J;  // device signs (null: J = I); rewritten by the sign pivoting
     const int4 *piv;
     int b;
@@ -423,45 +483,17 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
         s_need = 0;
         s_bad = 0;
     }
-    // A_P: the split partials (upper tiles) added in split order, mirrored
-    // to the lower part; 8 splits of 4 entries are loaded at a time
-    const double *base = a.partial + (size_t)pv * a.nsplit * W * W;
-    for (int e0 = tid; e0 < W * W; e0 += 4 * kPivotThreads) {
-        int off[4];
-        double acc[4];
+    // A_P, added up over the splits by k_gram_reduce
+    {
+        const double *src = a.ap + (size_t)pv * W * W;
+        constexpr int PER = W * W / kPivotThreads;
+        double v[PER];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = e0 + q * kPivotThreads;
-            int r = e % W, c = e / W;
-            if ((r / 16) > (c / 16) || ((r / 16) == (c / 16) && r > c)) {
-                const int t = r;
-                r = c;
-                c = t;
-            }
-            off[q] = (e < W * W) ? c * W + r : 0;
-            acc[q] = 0.0;
-        }
-        for (int sp0 = 0; sp0 < a.nsplit; sp0 += 8) {
-            double v[4][8];
+        for (int q = 0; q < PER; ++q) v[q] = src[tid + q * kPivotThreads];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    v[q][u] = (sp0 + u < a.nsplit) ? base[(size_t)(sp0 + u) * W * W + off[q]] : 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (sp0 + u < a.nsplit) acc[q] += v[q][u];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = e0 + q * kPivotThreads;
-            // an empty position has a zero Gram row and column: its diagonal
-            // entry becomes 1 (an identity row and column of A_P)
-            if (e < W * W)
-                A[(e / W) * P + (e % W)] =
-                    (e / W == e % W && !pivot_real(e % W, d, b)) ? 1.0 : acc[q];
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * kPivotThreads;
+            A[(e / W) * P + (e % W)] = v[q];
         }
     }
     __syncthreads();
@@ -788,6 +820,75 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
 // k_pivot_solve.  Unpivoted Cholesky only (the sign pivoting of Alg. 3.3
 // runs at W <= 64).  After a breakdown V_P is accumulated in LDS directly
 // while the inner sweeps run on G_P (R is not needed then).
+// One inner step's transform of pair `lane` in the W = 128 pivot solve:
+// the dot products of its columns over this wavefront's RPW rows (xr, yr),
+// as pairwise subtrees of RB rows and a pairwise tree over the subtrees,
+// meet the other wavefronts' in LDS (red; one barrier) and are added as
+// (w0 + w1) + (w2 + w3) in every wavefront, so all get the same totals.
+// Returns whether the pair rotates; c, sn, and same (trigonometric) then
+// hold the transform (else c = 1, sn = 0).
+template <int RPW, int RB, int NP>
+__device__ __forceinline__ bool log_pair_transform(const double *xr, const double *yr, double *red,
+                                                   int wave, int lane, double tol, bool same_sign,
+                                                   double &c, double &sn, bool &same, int &bad,
+                                                   bool &clamped)
+{
+    double pxx[RPW / RB], pyy[RPW / RB], pxy[RPW / RB];
+#pragma unroll
+    for (int g = 0; g < RPW / RB; ++g) {
+        double sxx[RB], syy[RB], sxy[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const double x = xr[g * RB + r], y = yr[g * RB + r];
+            sxx[r] = x * x;
+            syy[r] = y * y;
+            sxy[r] = x * y;
+        }
+#pragma unroll
+        for (int h = RB / 2; h > 0; h /= 2)
+#pragma unroll
+            for (int r = 0; r < h; ++r) {
+                sxx[r] += sxx[r + h];
+                syy[r] += syy[r + h];
+                sxy[r] += sxy[r + h];
+            }
+        pxx[g] = sxx[0];
+        pyy[g] = syy[0];
+        pxy[g] = sxy[0];
+    }
+#pragma unroll
+    for (int h = RPW / RB / 2; h > 0; h /= 2)
+#pragma unroll
+        for (int g = 0; g < h; ++g) {
+            pxx[g] += pxx[g + h];
+            pyy[g] += pyy[g + h];
+            pxy[g] += pxy[g + h];
+        }
+    red[(wave * 3 + 0) * NP + lane] = pxx[0];
+    red[(wave * 3 + 1) * NP + lane] = pyy[0];
+    red[(wave * 3 + 2) * NP + lane] = pxy[0];
+    __syncthreads();
+    double t[3][4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t[k][w] = red[(w * 3 + k) * NP + lane];
+    const double app = (t[0][0] + t[0][1]) + (t[0][2] + t[0][3]);
+    const double aqq = (t[1][0] + t[1][1]) + (t[1][2] + t[1][3]);
+    const double apq = (t[2][0] + t[2][1]) + (t[2][2] + t[2][3]);
+    bool act = true;
+    if (!finite3(app, aqq, apq)) {
+        bad = 1;
+        act = false;
+    }
+    act = act && needs_rotation(app, aqq, apq, tol);
+    same = act ? same_sign : true;
+    c = 1.0;
+    sn = 0.0;
+    clamped = act && transform_params(app, aqq, apq, same, c, sn);
+    return act;
+}
+
 constexpr int kLogThreads = 256;
 
 template <int W>
@@ -803,7 +904,7 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
     __shared__ double red[NW * 3 * NP];  // partial dots; in the replay, staged log entries
     __shared__ double dsh[W];          // Cholesky pivots d_j
     __shared__ signed char JP[W];
-    __shared__ int s_need, s_bad;
+    __shared__ int s_need, s_bad, s_brk;
     __shared__ unsigned long long s_rot[NW], s_cl[NW];
     const int pv = blockIdx.x;
     const int4 d = a.piv[pv];
@@ -817,54 +918,37 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
     if (tid == 0) {
         s_need = 0;
         s_bad = 0;
+        s_brk = 0;
     }
-    // A_P: the split partials (upper tiles) added in split order, mirrored
-    // to the lower part; empty positions get an identity row and column
-    const double *base = a.partial + (size_t)pv * a.nsplit * W * W;
-    for (int e0 = tid; e0 < W * W; e0 += 4 * kLogThreads) {
-        int off[4];
-        double acc[4];
+    // A_P, added up over the splits by k_gram_reduce (two halves of 32
+    // entries per thread in flight)
+    {
+        const double *src = a.ap + (size_t)pv * W * W;
+        constexpr int PER = W * W / kLogThreads / 2;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = e0 + q * kLogThreads;
-            int r = e % W, c = e / W;
-            if ((r / 16) > (c / 16) || ((r / 16) == (c / 16) && r > c)) {
-                const int t = r;
-                r = c;
-                c = t;
+        for (int h = 0; h < 2; ++h) {
+            double v[PER];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) v[q] = src[tid + (h * PER + q) * kLogThreads];
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int e = tid + (h * PER + q) * kLogThreads;
+                A[(e / W) * P + (e % W)] = v[q];
             }
-            off[q] = (e < W * W) ? c * W + r : 0;
-            acc[q] = 0.0;
-        }
-        for (int sp0 = 0; sp0 < a.nsplit; sp0 += 8) {
-            double v[4][8];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    v[q][u] = (sp0 + u < a.nsplit) ? base[(size_t)(sp0 + u) * W * W + off[q]] : 0.0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (sp0 + u < a.nsplit) acc[q] += v[q][u];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = e0 + q * kLogThreads;
-            if (e < W * W)
-                A[(e / W) * P + (e % W)] =
-                    (e / W == e % W && !pivot_real(e % W, d, b)) ? 1.0 : acc[q];
         }
     }
+    __syncthreads();
+    // skip test; the square roots of the diagonal (in dsh until the
+    // Cholesky factorisation needs it) are taken once
+    if (tid < W) dsh[tid] = sqrt(A[tid * P + tid]);
     __syncthreads();
     for (int e = tid; e < W * W; e += kLogThreads) {
         const int r = e % W, c = e / W;
         const double x = A[c * P + r];
         if (!isfinite(x)) s_bad = 1;
         if (r < c && (a.all_pairs || (r < b && c >= b))) {
-            const double arr = A[r * P + r], acc2 = A[c * P + c];
-            if (arr != 0.0 && acc2 != 0.0 && fabs(x) > a.tol * sqrt(arr) * sqrt(acc2)) s_need = 1;
+            if (A[r * P + r] != 0.0 && A[c * P + c] != 0.0 && fabs(x) > a.tol * dsh[r] * dsh[c])
+                s_need = 1;
         }
     }
     __syncthreads();
@@ -879,55 +963,81 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
         if (tid == 0) a.flag[pv] = 0;
         return;
     }
-    // Cholesky A_P = R^T R in place, right-looking, one barrier per column:
-    // with row j of R final (r_jl = a_jl / sqrt(d_j) in the upper triangle),
-    // the step finishes row j + 1 (d_{j+1} = a_{j+1,j+1} - r_{j,j+1}^2,
-    // r_{j+1,l} = (a_{j+1,l} - r_{j,j+1} r_jl) / sqrt(d_{j+1})) and subtracts
-    // r_ji r_jl from the entries (i, l), j + 2 <= i <= l, of the rows below;
-    // the two touch different rows.  The pivots d_j go to dsh (R's diagonal
-    // is sqrt(d_j)).  Every thread computes d_{j+1} from LDS after the
-    // barrier, so a breakdown is seen by all at once.
+    // Cholesky A_P = R^T R in place (R in the upper triangle), blocked
+    // right-looking with panels of NB rows: wavefront 0 factors a panel
+    // (rows j0 .. j0 + NB - 1 of R over all columns, each column's update of
+    // the later panel rows included; one wavefront's LDS accesses complete in
+    // order, so its columns need no barrier), then all threads subtract the
+    // panel's r_ji r_jl (j in the panel, in order) from the trailing entries
+    // (i, l), j0 + NB <= i <= l.  The pivots d_j go to dsh (R's diagonal is
+    // sqrt(d_j)).  Wavefront 0 reports a breakdown (d_j <= 0) in s_brk,
+    // which every thread reads after the barrier.
+    constexpr int NB = 16;
     bool broke = false;
-    {
-        const double d0 = A[0];
-        if (!(d0 > 0.0)) {
-            broke = true;
-        } else {
-            const double r00 = sqrt(d0);
-            for (int l = 1 + tid; l < W; l += kLogThreads) A[l * P] = A[l * P] / r00;
-            if (tid == 0) dsh[0] = d0;
+    for (int j0 = 0; j0 < W; j0 += NB) {
+        if (wave == 0) {
+            // The panel rows j0 .. j0 + NB - 1 at columns l0 = j0 + lane and
+            // l1 = j0 + 64 + lane (clamped to W - 1: a clamped lane repeats
+            // the work of the lane that owns column W - 1) stay in registers
+            // while the panel is factored: the entry (j, j) and the row-j
+            // entries r_ju of the columns of later panel rows come from the
+            // lanes that hold them (readlane), so the column loop makes no
+            // LDS access.  Every update is applied to all columns: below the
+            // diagonal (l < row) the values are junk that the factorisation
+            // never reads, and the strict lower triangle is zeroed afterwards.
+            const int l0 = min(j0 + lane, W - 1), l1 = min(j0 + 64 + lane, W - 1);
+            double p0[NB], p1[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                p0[u] = A[l0 * P + j0 + u];
+                p1[u] = A[l1 * P + j0 + u];
+            }
+            bool brk = false;
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+                const int j = j0 + jj;
+                const double dj = read_lane(p0[jj], jj);   // lane jj holds column j
+                // a breakdown (the same in every lane) voids the whole pivot:
+                // the panel runs on (on junk) so that the loop stays unrolled
+                brk = brk || !(dj > 0.0);
+                const double rjj = sqrt(dj);
+                if (lane == 0) dsh[j] = dj;
+                // row j of R at this lane's columns l > j (l = j keeps d_j)
+                const double s0 = p0[jj] / rjj, s1 = p1[jj] / rjj;
+                p0[jj] = (l0 > j) ? s0 : p0[jj];
+                p1[jj] = (l1 > j) ? s1 : p1[jj];
+                // the later rows of the panel: a_ul -= r_ju r_jl
+#pragma unroll
+                for (int u = jj + 1; u < NB; ++u) {
+                    const double rju = read_lane(p0[jj], u);   // lane u holds column j0 + u
+                    p0[u] -= rju * p0[jj];
+                    p1[u] -= rju * p1[jj];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                A[l0 * P + j0 + u] = p0[u];
+                A[l1 * P + j0 + u] = p1[u];
+            }
+            if (brk && lane == 0) s_brk = 1;
         }
         __syncthreads();
-    }
-    for (int j = 0; j + 1 < W && !broke; ++j) {
-        const int j1 = j + 1;
-        const double rj1 = A[j1 * P + j];
-        const double d1 = A[j1 * P + j1] - rj1 * rj1;
-        if (!(d1 > 0.0)) {
+        if (s_brk) {
             broke = true;
             break;
         }
-        const double r11 = sqrt(d1);
-        for (int l = j1 + 1 + tid; l < W; l += kLogThreads)
-            A[l * P + j1] = (A[l * P + j1] - rj1 * A[l * P + j]) / r11;
-        // the trailing rows over a 16 x 16 thread grid; row j's entries of
-        // this thread's columns i are read once
-        const int tl = tid >> 4, ti = tid & 15;
-        double ri[W / 16];
+        const int t0 = j0 + NB;
+        for (int l = t0 + (tid >> 4); l < W; l += kLogThreads / 16) {
+            double rl[NB];
 #pragma unroll
-        for (int u = 0; u < W / 16; ++u) {
-            const int i = j + 2 + ti + 16 * u;
-            ri[u] = (i < W) ? A[i * P + j] : 0.0;
-        }
-        for (int l = j + 2 + tl; l < W; l += 16) {
-            const double rl = A[l * P + j];
+            for (int u = 0; u < NB; ++u) rl[u] = A[l * P + j0 + u];
+            for (int i = t0 + (tid & 15); i <= l; i += 16) {
+                double acc = A[l * P + i];
 #pragma unroll
-            for (int u = 0; u < W / 16; ++u) {
-                const int i = j + 2 + ti + 16 * u;
-                if (i <= l) A[l * P + i] -= ri[u] * rl;
+                for (int u = 0; u < NB; ++u) acc -= A[i * P + j0 + u] * rl[u];
+                A[l * P + i] = acc;
             }
         }
-        if (tid == 0) dsh[j1] = d1;
         __syncthreads();
     }
     if (broke && !a.G) {
@@ -942,9 +1052,10 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
     unsigned long long rot = 0, ncl = 0;
     int bad = 0;
     const int sweeps = a.full_block ? a.max_inner : 1;
-    const int nsteps = inner_steps(a.all_pairs, W);
     double2 *log = a.vlog + (size_t)pv * a.log_stride;
-    int logged = 0;   // inner sweeps in the log
+    int logged = 0;       // inner sweeps in the log
+    int vp_layout = 1;    // V_P in A: 0 row-major, 1 column-major, 2 column-major with
+                          // the two halves of the columns swapped
     if (!broke) {
         // R: the diagonal becomes sqrt(d_j), the strict lower triangle zero
         for (int e = tid; e < W * W; e += kLogThreads) {
@@ -953,153 +1064,179 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
             else if (r > c) A[c * P + r] = 0.0;
         }
         __syncthreads();
-        const int r0 = wave * RPW;
-        // I x J steps (block-oriented after the first step of a sweep): lane k
-        // pairs column k of block I with a column of block J that changes
-        // every step, so column k stays in registers for the whole inner
-        // sweep (and is not written back: R is not needed after the sweeps)
-        const bool keep_x = !a.all_pairs;
-        double xr[RPW];
-        if (keep_x) {
+        // The inner sweeps, with the inner ordering fixed at compile time.
+        //   I x J pairs (block-oriented after the first step of a sweep):
+        //     lane k pairs column k of block I with column (k + s) mod b of
+        //     block J at step s, so R's and V_P's block-I columns stay in
+        //     registers for the whole sweep; V_P's block-J columns take the
+        //     LDS of R's block-I columns, and both are rotated in the step.
+        //   all pairs (the first step of a sweep, and full block): both
+        //     columns of a pair change every step; the steps log their
+        //     transforms, and V_P is formed from the log afterwards in the
+        //     LDS of R (it does not fit beside it).
+        auto sweeps_and_replay = [&](auto all_c) {
+            constexpr bool ALL = decltype(all_c)::value;
+            const int nsteps = inner_steps(ALL, W);
+            const int r0 = wave * RPW;
+            if constexpr (!ALL) {
+                constexpr int HB = W / 2;
+                double xr[RPW], vx[RPW];
 #pragma unroll
-            for (int r = 0; r < RPW; ++r) xr[r] = A[lane * P + r0 + r];
-        }
-        for (int it = 0; it < sweeps; ++it) {
-            unsigned long long rot_it = 0;
-            for (int s = 0; s < nsteps; ++s) {
-                const int2 pq = inner_pair(a.all_pairs, W, s, lane);
-                double *yp = A + pq.x * P + r0, *yq = A + pq.y * P + r0;
-                double yr[RPW];
-                if (!keep_x) {
-#pragma unroll
-                    for (int r = 0; r < RPW; ++r) xr[r] = yp[r];
+                for (int r = 0; r < RPW; ++r) xr[r] = A[lane * P + r0 + r];
+                __syncthreads();   // R's block-I columns are read before the LDS takes V_J
+                // V_J (block-J columns of V_P := I) at the slots of R's
+                // block-I columns: slot c holds column b + c
+                for (int e = tid; e < HB * W; e += kLogThreads) {
+                    const int r = e % W, c = e / W;
+                    A[c * P + r] = (r == HB + c) ? 1.0 : 0.0;
                 }
 #pragma unroll
-                for (int r = 0; r < RPW; ++r) yr[r] = yq[r];
-                // partial dot products over this wavefront's rows: pairwise
-                // subtrees of RB rows, then a pairwise tree over the subtrees
-                double pxx[RPW / RB], pyy[RPW / RB], pxy[RPW / RB];
+                for (int r = 0; r < RPW; ++r) vx[r] = (r0 + r == lane) ? 1.0 : 0.0;
+                __syncthreads();
+                unsigned long long rot_it = 0;
+                for (int s = 0; s < nsteps; ++s) {
+                    const int cj = (lane + s) % HB;   // the block-J column of the pair
+                    double *yq = A + (HB + cj) * P + r0, *vq = A + cj * P + r0;
+                    double yr[RPW], vy[RPW];
 #pragma unroll
-                for (int g = 0; g < RPW / RB; ++g) {
-                    double sxx[RB], syy[RB], sxy[RB];
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) {
-                        const double x = xr[g * RB + r], y = yr[g * RB + r];
-                        sxx[r] = x * x;
-                        syy[r] = y * y;
-                        sxy[r] = x * y;
+                    for (int r = 0; r < RPW; ++r) {
+                        yr[r] = yq[r];
+                        vy[r] = vq[r];
                     }
+                    double c, sn;
+                    bool same, cl;
+                    const bool act = log_pair_transform<RPW, RB, NP>(
+                        xr, yr, red, wave, lane, a.tol, JP[lane] == JP[HB + cj], c, sn, same, bad, cl);
+                    if (cl && wave == 0) ++ncl;
+                    if (act) {
 #pragma unroll
-                    for (int h = RB / 2; h > 0; h /= 2)
-#pragma unroll
-                        for (int r = 0; r < h; ++r) {
-                            sxx[r] += sxx[r + h];
-                            syy[r] += syy[r + h];
-                            sxy[r] += sxy[r + h];
+                        for (int r = 0; r < RPW; ++r) {
+                            rotate_elems(xr[r], yr[r], c, sn, same);
+                            rotate_elems(vx[r], vy[r], c, sn, same);
                         }
-                    pxx[g] = sxx[0];
-                    pyy[g] = syy[0];
-                    pxy[g] = sxy[0];
-                }
 #pragma unroll
-                for (int h = RPW / RB / 2; h > 0; h /= 2)
-#pragma unroll
-                    for (int g = 0; g < h; ++g) {
-                        pxx[g] += pxx[g + h];
-                        pyy[g] += pyy[g + h];
-                        pxy[g] += pxy[g + h];
+                        for (int r = 0; r < RPW; ++r) {
+                            yq[r] = yr[r];
+                            vq[r] = vy[r];
+                        }
+                        if (wave == 0) ++rot_it;
                     }
-                red[(wave * 3 + 0) * NP + lane] = pxx[0];
-                red[(wave * 3 + 1) * NP + lane] = pyy[0];
-                red[(wave * 3 + 2) * NP + lane] = pxy[0];
-                __syncthreads();
-                // (w0 + w1) + (w2 + w3): the same order in every wavefront
-                static_assert(NW == 4, "four wavefronts");
-                double t[3][NW];
-#pragma unroll
-                for (int w = 0; w < NW; ++w)
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) t[k][w] = red[(w * 3 + k) * NP + lane];
-                const double app = (t[0][0] + t[0][1]) + (t[0][2] + t[0][3]);
-                const double aqq = (t[1][0] + t[1][1]) + (t[1][2] + t[1][3]);
-                const double apq = (t[2][0] + t[2][1]) + (t[2][2] + t[2][3]);
-                bool act = true;
-                if (!finite3(app, aqq, apq)) {
-                    bad = 1;
-                    act = false;
+                    __syncthreads();
                 }
-                act = act && needs_rotation(app, aqq, apq, a.tol);
-                const bool same = act ? (JP[pq.x] == JP[pq.y]) : true;
-                double c = 1.0, sn = 0.0;
-                if (act && transform_params(app, aqq, apq, same, c, sn) && wave == 0) ++ncl;
-                if (wave == 0)
-                    log[((size_t)it * nsteps + s) * NP + lane] =
-                        act ? make_double2(same ? c : -c, sn) : make_double2(1.0, 0.0);
-                if (act) {
+                rot += rot_it;
+                // V_P's block-I columns to the (now free) slots of R's
+                // block-J columns: slot b + k holds column k
 #pragma unroll
-                    for (int r = 0; r < RPW; ++r) rotate_elems(xr[r], yr[r], c, sn, same);
-                    if (!keep_x) {
+                for (int r = 0; r < RPW; ++r) A[(HB + lane) * P + r0 + r] = vx[r];
+                vp_layout = 2;
+                __syncthreads();
+            } else {
+                for (int it = 0; it < sweeps; ++it) {
+                    unsigned long long rot_it = 0;
+                    for (int s = 0; s < nsteps; ++s) {
+                        const int2 pq = inner_pair_t<ALL>(W, s, lane);
+                        double *yp = A + pq.x * P + r0, *yq = A + pq.y * P + r0;
+                        double xr[RPW], yr[RPW];
 #pragma unroll
-                        for (int r = 0; r < RPW; ++r) yp[r] = xr[r];
+                        for (int r = 0; r < RPW; ++r) {
+                            xr[r] = yp[r];
+                            yr[r] = yq[r];
+                        }
+                        double c, sn;
+                        bool same, cl;
+                        const bool act = log_pair_transform<RPW, RB, NP>(
+                            xr, yr, red, wave, lane, a.tol, JP[pq.x] == JP[pq.y], c, sn, same, bad, cl);
+                        if (cl && wave == 0) ++ncl;
+                        if (wave == 0)
+                            log[((size_t)it * nsteps + s) * NP + lane] =
+                                act ? make_double2(same ? c : -c, sn) : make_double2(1.0, 0.0);
+                        if (act) {
+#pragma unroll
+                            for (int r = 0; r < RPW; ++r) rotate_elems(xr[r], yr[r], c, sn, same);
+#pragma unroll
+                            for (int r = 0; r < RPW; ++r) {
+                                yp[r] = xr[r];
+                                yq[r] = yr[r];
+                            }
+                            if (wave == 0) ++rot_it;
+                        }
+                        __syncthreads();
                     }
-#pragma unroll
-                    for (int r = 0; r < RPW; ++r) yq[r] = yr[r];
-                    if (wave == 0) ++rot_it;
+                    ++logged;
+                    rot += rot_it;
+                    const double wr = wave_sum((double)rot_it);
+                    if (lane == 0) s_rot[wave] = (unsigned long long)wr;
+                    __syncthreads();
+                    // only wavefront 0 counted, so its total is the step's
+                    const unsigned long long tot = s_rot[0];
+                    __syncthreads();
+                    if (tot == 0) break;
+                }
+                // V_P := I (row-major, pitch P), then the logged transforms are
+                // replayed on its rows.  Lanes l and l + 32 of wavefront w own row
+                // 32 w + l mod 32 and take the first and the second half of each
+                // step's pairs: the pairs of a step are disjoint, and the LDS accesses
+                // of one wavefront complete in order, so the halves need no barrier
+                // between steps.  The log passes through LDS (the red area) RC steps
+                // at a time, the next chunk loaded while the current one is replayed;
+                // its global writes were made visible first.
+                __threadfence();
+                for (int e = tid; e < W * W; e += kLogThreads) {
+                    const int r = e / W, c = e % W;
+                    A[r * P + c] = (r == c) ? 1.0 : 0.0;
+                }
+                constexpr int RC = kLogThreads / NP;   // steps per chunk: one entry per thread
+                static_assert(RC * NP == kLogThreads && RC * NP * 2 <= NW * 3 * NP, "log chunk in red");
+                double2 *stage = (double2 *)red;
+                const long total = (long)logged * nsteps;   // logged steps
+                const int row = wave * 32 + (lane & 31), half = lane >> 5;
+                double *vr = A + row * P;
+                double2 nxt = (total * NP > tid) ? log[tid] : make_double2(1.0, 0.0);
+                for (long c0 = 0; c0 < total; c0 += RC) {
+                    __syncthreads();   // the previous chunk is no longer read
+                    stage[tid] = nxt;
+                    __syncthreads();
+                    const long e_next = (c0 + RC) * NP + tid;
+                    if (e_next < total * NP) nxt = log[e_next];
+                    for (int sc = 0; sc < RC && c0 + sc < total; ++sc) {
+                        const int s = (int)((c0 + sc) % nsteps);   // step within its inner sweep
+                        const double2 *le = stage + sc * NP + half * (NP / 2);
+                        // groups of RG pairs: all loads, then the arithmetic, then the
+                        // stores (the pairs of a step are disjoint); a pair that was
+                        // not rotated has the entry (1, 0), whose transform leaves
+                        // both elements as they are, so there is no branch
+                        constexpr int RG = 16;
+        #pragma unroll 1
+                        for (int i0 = 0; i0 < NP / 2; i0 += RG) {
+                            double2 e[RG];
+                            int2 pq[RG];
+                            double x[RG], y[RG];
+        #pragma unroll
+                            for (int u = 0; u < RG; ++u) {
+                                e[u] = le[i0 + u];
+                                pq[u] = inner_pair_t<ALL>(W, s, half * (NP / 2) + i0 + u);
+                                x[u] = vr[pq[u].x];
+                                y[u] = vr[pq[u].y];
+                            }
+        #pragma unroll
+                            for (int u = 0; u < RG; ++u)
+                                rotate_elems(x[u], y[u], fabs(e[u].x), e[u].y, e[u].x > 0.0);
+        #pragma unroll
+                            for (int u = 0; u < RG; ++u) {
+                                vr[pq[u].x] = x[u];
+                                vr[pq[u].y] = y[u];
+                            }
+                        }
+                    }
                 }
                 __syncthreads();
+                vp_layout = 0;
             }
-            ++logged;
-            rot += rot_it;
-            const double wr = wave_sum((double)rot_it);
-            if (lane == 0) s_rot[wave] = (unsigned long long)wr;
-            __syncthreads();
-            // only wavefront 0 counted, so its total is the step's
-            const unsigned long long tot = s_rot[0];
-            __syncthreads();
-            if (tot == 0) break;
-        }
-        // V_P := I (row-major, pitch P), then the logged transforms are
-        // replayed on its rows.  Lanes l and l + 32 of wavefront w own row
-        // 32 w + l mod 32 and take the first and the second half of each
-        // step's pairs: the pairs of a step are disjoint, and the LDS accesses
-        // of one wavefront complete in order, so the halves need no barrier
-        // between steps.  The log passes through LDS (the red area) RC steps
-        // at a time, the next chunk loaded while the current one is replayed;
-        // its global writes were made visible first.
-        __threadfence();
-        for (int e = tid; e < W * W; e += kLogThreads) {
-            const int r = e / W, c = e % W;
-            A[r * P + c] = (r == c) ? 1.0 : 0.0;
-        }
-        constexpr int RC = kLogThreads / NP;   // steps per chunk: one entry per thread
-        static_assert(RC * NP == kLogThreads && RC * NP * 2 <= NW * 3 * NP, "log chunk in red");
-        double2 *stage = (double2 *)red;
-        const long total = (long)logged * nsteps;   // logged steps
-        const int row = wave * 32 + (lane & 31), half = lane >> 5;
-        double *vr = A + row * P;
-        double2 nxt = (total * NP > tid) ? log[tid] : make_double2(1.0, 0.0);
-        for (long c0 = 0; c0 < total; c0 += RC) {
-            __syncthreads();   // the previous chunk is no longer read
-            stage[tid] = nxt;
-            __syncthreads();
-            const long e_next = (c0 + RC) * NP + tid;
-            if (e_next < total * NP) nxt = log[e_next];
-            for (int sc = 0; sc < RC && c0 + sc < total; ++sc) {
-                const int s = (int)((c0 + sc) % nsteps);   // step within its inner sweep
-                const double2 *le = stage + sc * NP + half * (NP / 2);
-#pragma unroll 4
-                for (int i = 0; i < NP / 2; ++i) {
-                    const double2 e = le[i];
-                    if (e.x == 1.0 && e.y == 0.0) continue;
-                    const int2 pq = inner_pair(a.all_pairs, W, s, half * (NP / 2) + i);
-                    double x = vr[pq.x], y = vr[pq.y];
-                    rotate_elems(x, y, fabs(e.x), e.y, e.x > 0.0);
-                    vr[pq.x] = x;
-                    vr[pq.y] = y;
-                }
-            }
-        }
-        __syncthreads();
+        };
+        if (a.all_pairs)
+            sweeps_and_replay(std::true_type{});
+        else
+            sweeps_and_replay(std::false_type{});
     } else {
         // G_P is transformed in place; V_P (column-major, pitch P) collects
         // the transforms for V
@@ -1147,7 +1284,9 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
         double *out = a.vpt + (size_t)pv * W * W;
         for (int e = tid; e < W * W; e += kLogThreads) {
             const int r = e / W, c = e % W;
-            out[e] = broke ? A[c * P + r] : A[r * P + c];
+            out[e] = vp_layout == 0   ? A[r * P + c]
+                     : vp_layout == 1 ? A[c * P + r]
+                                      : A[((c + W / 2) % W) * P + r];
         }
     }
 }
@@ -1466,11 +1605,13 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     else
         k_gram<W, T><<<dim3(npiv, nsplit), 256, 0, st>>>(G, a.m, ldg, piv, rows_per_split, ws->partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_gram_reduce<W><<<dim3((W * W + 255) / 256, npiv), 256, 0, st>>>(ws->partial, nsplit, piv, a.b,
+                                                                     ws->ap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = a.timer->end(st)) != hipSuccess) return e;
 
     PivotSolveArgs p;
-    p.partial = ws->partial;
-    p.nsplit = nsplit;
+    p.ap = ws->ap;
     p.J = a.dJ;
     p.piv = piv;
     p.b = a.b;
@@ -1539,6 +1680,8 @@ static int prepare_steps(BlockWorkspace *ws, const BlockRunArgs &a, int *nsplit_
     rc = grow(&ws->partial, &ws->capPartial, (size_t)npiv * nsplit * W * W);
     if (rc) return rc;
     rc = grow(&ws->vp, &ws->capVp, (size_t)npiv * W * W);
+    if (rc) return rc;
+    rc = grow(&ws->ap, &ws->capAp, (size_t)npiv * W * W);
     if (rc) return rc;
     rc = grow(&ws->flags, &ws->capFlags, (size_t)npiv);
     if (rc) return rc;
@@ -1721,6 +1864,7 @@ void block_workspace_free(BlockWorkspace *ws)
     if (ws->vp) (void)hipFree(ws->vp);
     if (ws->flags) (void)hipFree(ws->flags);
     if (ws->vlog) (void)hipFree(ws->vlog);
+    if (ws->ap) (void)hipFree(ws->ap);
     if (ws->g32) (void)hipFree(ws->g32);
     if (ws->v32) (void)hipFree(ws->v32);
     if (ws->t64) (void)hipFree(ws->t64);
