@@ -751,13 +751,25 @@ def main():
             if lam_ref is None:
                 gate.update({"eigenvalues": meta["reason"], "ok": False})
             else:
-                err = gates.rel_err(lam_gpu, lam_ref)
-                gate.update({"rel_eig_err_vs_oracle": err, "limit": gates.REL_TOL,
-                             "oracle": meta["oracle"], "oracle_sweeps": meta["sweeps"],
+                # the eigenvalue gate of oracle/gates.py: 1e-12 against the
+                # cached FP64 oracle solve, else the bound (1.2) against its
+                # cached 80-bit run (when one was made for this input)
+                truth = None
+                if "truth" in meta:
+                    lam80 = np.load(os.path.join(GOLDEN, GOLDEN_OF[args.workload] + ".lam80.npy"),
+                                    allow_pickle=False)
+                    truth = lambda: lam80
+                res = gates.eig_gate(wl.G, lam_gpu, lam_ref, truth, meta.get("kappa_colscaled"))
+                gate.update(res)
+                gate.update({"oracle": meta["oracle"], "oracle_sweeps": meta["sweeps"],
                              "oracle_input_sha256": meta["input_sha256"][:16],
-                             "ok": gate["ok"] and err <= gates.REL_TOL})
+                             "ok": gate["ok"] and res["ok"]})
+                if "truth" in meta:
+                    gate["high_precision_oracle"] = meta["truth"]["oracle"]
                 if compare is not None:
-                    compare["rel_eig_err_vs_oracle"] = gates.rel_err(compare["lam"], lam_ref)
+                    cres = gates.eig_gate(wl.G, compare["lam"], lam_ref, truth,
+                                          meta.get("kappa_colscaled"))
+                    compare["accuracy"] = cres
             # the threaded oracle (the disjoint pivots of each step on all host
             # cores; bit for bit the sequential oracle) timed on the first
             # steps of a sweep: more steps until ~15 s of CPU work

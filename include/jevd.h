@@ -266,8 +266,10 @@ int jevd_adjoint(jevd_handle_t h, int batch, int m, int n, const double *G, int 
  * caller's G (device, m x n, ld ldg; not modified) with J, tol and opts
  * (pivot and precision are kept; variant, block and accumulate_v are
  * varied/ignored) once for each candidate -- pointwise (FP64 without
- * pivoting only), and block-oriented and full block at every admissible
- * b in {16, 32, 64} -- forming V when want_v, and records the fastest
+ * pivoting, n <= 2048 only), and block-oriented and full block at every
+ * admissible b in {16, 32, 64} (b = 16 for n <= 2048 only: above that it and
+ * the pointwise solve take several times as long as the wider blocks) --
+ * forming V when want_v, and records the fastest
  * (wall time to convergence) for (m, n) in the process's tune table, which
  * is also written to the tune file.  *block, *variant, *ms (each may be
  * NULL) receive the winner (block 0 for pointwise).  Returns JEVD_OK,

@@ -48,17 +48,19 @@ def bound_12(G):
     return 64.0 * n * U * kappa_colscaled(G)
 
 
-def eig_gate(G, lam_gpu, lam_fp64, truth=None):
+def eig_gate(G, lam_gpu, lam_fp64, truth=None, kappa=None):
     """Applies the gate.  lam_fp64: the FP64 oracle's eigenvalues; truth: a
     callable returning a high-precision oracle run's eigenvalues (called
-    only when check 1 fails).  Returns a dict with 'ok' and the figures."""
+    only when check 1 fails); kappa: kappa_colscaled(G) if already known.
+    Returns a dict with 'ok' and the figures."""
     err = rel_err(lam_gpu, lam_fp64)
     out = {"rel_eig_err_vs_oracle": err, "limit": REL_TOL, "ok": err <= REL_TOL}
     if out["ok"] or truth is None:
         return out
     lam_true = truth()
     e_gpu = rel_err(lam_gpu, lam_true)
-    bnd = bound_12(G)
+    n = np.asarray(G).shape[1]
+    bnd = 64.0 * n * U * (kappa if kappa is not None else kappa_colscaled(G))
     out.update({"rel_eig_err_vs_high_precision": e_gpu,
                 "fp64_oracle_err_vs_high_precision": rel_err(lam_fp64, lam_true),
                 "bound_64_n_u_kappa": bnd, "ok": e_gpu <= bnd})

@@ -583,11 +583,14 @@ int jevd_autotune(jevd_handle_t h, int m, int n, const double *G, int ldg, const
         int variant, block;
     };
     std::vector<Cand> cands;
-    if (o.pivot == JEVD_PIVOT_NONE && o.precision == JEVD_PREC_FP64)
+    // Above n = 2048 the pointwise solve (n steps per sweep, each streaming
+    // all of G) and b = 16 (n / 16 steps per sweep) take several times as
+    // long as the wider blocks, so they are not tried there.
+    if (o.pivot == JEVD_PIVOT_NONE && o.precision == JEVD_PREC_FP64 && n <= 2048)
         cands.push_back({JEVD_VAR_POINTWISE, 0});
     for (int v : {JEVD_VAR_BLOCK_ORIENTED, JEVD_VAR_FULL_BLOCK})
         for (int b : {16, 32, 64})
-            if (block_options_supported(m, n, b, o.pivot == JEVD_PIVOT_SIGN))
+            if ((b > 16 || n <= 2048) && block_options_supported(m, n, b, o.pivot == JEVD_PIVOT_SIGN))
                 cands.push_back({v, b});
     int best = -1;
     double best_ms = 0.0;

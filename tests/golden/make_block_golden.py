@@ -12,9 +12,15 @@ of each step spread over all host cores; that threaded run is bit for bit
 the sequential oracle (tests/test_oracle_pins.py pins it).
 
     python tests/golden/make_block_golden.py spd-graded-T-n8192 [...]
+    python tests/golden/make_block_golden.py --truth hyperbolic-graded-n4096 [...]
 
 Each workload gives <name>.lam.npy (eigenvalues in column order) and
 <name>.json (input hash, oracle configuration, status, sweeps, time, host).
+--truth adds, for a workload already cached, the same oracle run in 80-bit
+long double (<name>.lam80.npy, whose error is smaller by 2^11 than an FP64
+run's) and kappa_2 of the factor with its columns scaled to unit norm: the
+high-precision reference and the condition number of the relative accuracy
+bound (1.2) that the eigenvalue gate falls back to (oracle/gates.py).
 """
 import json
 import os
@@ -54,6 +60,30 @@ def host():
     return "%s, %d logical CPUs" % (model, os.cpu_count())
 
 
+def truth(names):
+    from oracle import gates
+    for name in names:
+        wl, opt = workload(name)
+        meta_path = os.path.join(HERE, name + ".json")
+        meta = json.load(open(meta_path))
+        if meta["input_sha256"] != W.input_sha256(wl.G):
+            raise SystemExit("%s: input differs from the cached FP64 solve" % name)
+        t = time.perf_counter()
+        r = O.block_jevd(wl.G, wl.J, wl.n * 1e-19, want_v=False, nthreads=0, prec="l", **opt)
+        dt = time.perf_counter() - t
+        if r.status != 0:
+            raise SystemExit("%s: 80-bit oracle status %d" % (name, r.status))
+        np.save(os.path.join(HERE, name + ".lam80.npy"), r.lam)
+        meta["truth"] = {"oracle": "block_jevd 80-bit long double " + json.dumps(opt),
+                         "tol": wl.n * 1e-19, "sweeps": r.sweeps, "seconds": round(dt, 1),
+                         "command": "python tests/golden/make_block_golden.py --truth " + name}
+        meta["kappa_colscaled"] = gates.kappa_colscaled(wl.G)
+        with open(meta_path, "w") as f:
+            json.dump(meta, f, indent=1)
+            f.write("\n")
+        print(json.dumps(meta["truth"]), meta["kappa_colscaled"], flush=True)
+
+
 def main(names):
     for name in names:
         t = time.perf_counter()
@@ -80,4 +110,7 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:])
+    if sys.argv[1:2] == ["--truth"]:
+        truth(sys.argv[2:])
+    else:
+        main(sys.argv[1:])
