@@ -16,6 +16,12 @@ struct BlockWorkspace {
     double *ap = nullptr;       // per pivot the W x W Gram, added up over the splits
     size_t capPartial = 0, capVp = 0, capFlags = 0, capVlog = 0, capAp = 0;
     void *tables = nullptr;     // block and inner orderings (device copies)
+    // V's half of the update runs on a second stream, one step behind (two
+    // parities of vp and flags); evReady: the solve's stream has reached
+    // the point where the next V update may start; evVdone[p]: the V update
+    // that read parity p is done; evJoin: stream hand-over
+    hipStream_t vstream = nullptr;
+    hipEvent_t evReady = nullptr, evVdone[2] = {nullptr, nullptr}, evJoin = nullptr;
     // mixed precision: FP32 iterate and transform, FP64 work arrays
     float *g32 = nullptr, *v32 = nullptr;
     double *t64 = nullptr, *w64 = nullptr;

@@ -820,18 +820,19 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
 // k_pivot_solve.  Unpivoted Cholesky only (the sign pivoting of Alg. 3.3
 // runs at W <= 64).  After a breakdown V_P is accumulated in LDS directly
 // while the inner sweeps run on G_P (R is not needed then).
-// One inner step's transform of pair `lane` in the W = 128 pivot solve:
+// One inner step's transform of pair `lane` in the W = 128 pivot solves:
 // the dot products of its columns over this wavefront's RPW rows (xr, yr),
 // as pairwise subtrees of RB rows and a pairwise tree over the subtrees,
-// meet the other wavefronts' in LDS (red; one barrier) and are added as
-// (w0 + w1) + (w2 + w3) in every wavefront, so all get the same totals.
-// Returns whether the pair rotates; c, sn, and same (trigonometric) then
-// hold the transform (else c = 1, sn = 0).
-template <int RPW, int RB, int NP>
-__device__ __forceinline__ bool log_pair_transform(const double *xr, const double *yr, double *red,
-                                                   int wave, int lane, double tol, bool same_sign,
-                                                   double &c, double &sn, bool &same, int &bad,
-                                                   bool &clamped)
+// meet the other NW - 1 wavefronts' in LDS (red; one barrier) and are added
+// pairwise in wavefront order ((w0 + w1) + (w2 + w3) for NW = 4) in every
+// wavefront, so all get the same totals.  Returns whether the pair rotates;
+// c, sn, and same (trigonometric) then hold the transform (else c = 1,
+// sn = 0).
+template <int RPW, int RB, int NW, int NP>
+__device__ __forceinline__ bool pair_transform(const double *xr, const double *yr, double *red,
+                                               int wave, int lane, double tol, bool same_sign,
+                                               double &c, double &sn, bool &same, int &bad,
+                                               bool &clamped)
 {
     double pxx[RPW / RB], pyy[RPW / RB], pxy[RPW / RB];
 #pragma unroll
@@ -868,14 +869,18 @@ __device__ __forceinline__ bool log_pair_transform(const double *xr, const doubl
     red[(wave * 3 + 1) * NP + lane] = pyy[0];
     red[(wave * 3 + 2) * NP + lane] = pxy[0];
     __syncthreads();
-    double t[3][4];
+    double t[3][NW];
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
+    for (int w = 0; w < NW; ++w)
 #pragma unroll
         for (int k = 0; k < 3; ++k) t[k][w] = red[(w * 3 + k) * NP + lane];
-    const double app = (t[0][0] + t[0][1]) + (t[0][2] + t[0][3]);
-    const double aqq = (t[1][0] + t[1][1]) + (t[1][2] + t[1][3]);
-    const double apq = (t[2][0] + t[2][1]) + (t[2][2] + t[2][3]);
+#pragma unroll
+    for (int h = 1; h < NW; h *= 2)
+#pragma unroll
+        for (int w = 0; w < NW; w += 2 * h)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) t[k][w] += t[k][w + h];
+    const double app = t[0][0], aqq = t[1][0], apq = t[2][0];
     bool act = true;
     if (!finite3(app, aqq, apq)) {
         bad = 1;
@@ -887,6 +892,158 @@ __device__ __forceinline__ bool log_pair_transform(const double *xr, const doubl
     sn = 0.0;
     clamped = act && transform_params(app, aqq, apq, same, c, sn);
     return act;
+}
+
+// A_P (column-major W x W, from k_gram_reduce) into LDS with pitch W + 1:
+// thread tid takes the entries tid + q NT, up to 32 loads in flight.
+template <int W, int NT>
+__device__ __forceinline__ void pivot_load_gram(const double *__restrict__ src, double *A, int tid)
+{
+    constexpr int P = W + 1;
+    constexpr int PER = W * W / NT;
+    constexpr int BATCH = PER < 32 ? PER : 32;
+    static_assert(PER % BATCH == 0, "whole batches");
+#pragma unroll
+    for (int h = 0; h < PER / BATCH; ++h) {
+        double v[BATCH];
+#pragma unroll
+        for (int q = 0; q < BATCH; ++q) v[q] = src[tid + (h * BATCH + q) * NT];
+#pragma unroll
+        for (int q = 0; q < BATCH; ++q) {
+            const int e = tid + (h * BATCH + q) * NT;
+            A[(e / W) * P + (e % W)] = v[q];
+        }
+    }
+}
+
+// The skip test of a pivot, before the factorisation: need = some pair
+// (r, c), r < c, of the inner ordering (all pairs, or block I x block J)
+// has both columns nonzero and |a_rc| > tol sqrt(a_rr) sqrt(a_cc) (dsh holds
+// the square roots of the diagonal); bad = some entry is not finite.  Thread
+// tid checks row tid mod W at the columns tid / W + q NT / W, without
+// branches.
+template <int W, int NT>
+__device__ __forceinline__ void pivot_skip_test(const double *A, const double *dsh, int b,
+                                                bool all_pairs, double tol, int tid, bool &need,
+                                                bool &bad)
+{
+    constexpr int P = W + 1;
+    static_assert(NT % W == 0, "one row per thread");
+    const int r = tid % W;
+    const double dr = dsh[r];
+    int nd = 0, bd = 0;
+#pragma unroll 8
+    for (int q = 0; q < W * W / NT; ++q) {
+        const int c = tid / W + q * (NT / W);
+        const double x = A[c * P + r];
+        const double dc = dsh[c];
+        bd |= !isfinite(x);
+        const int pair = (r < c) & (all_pairs | ((r < b) & (c >= b)));
+        nd |= pair & (dr != 0.0) & (dc != 0.0) & (fabs(x) > tol * dr * dc);
+    }
+    need = nd != 0;
+    bad = bd != 0;
+}
+
+// Unpivoted Cholesky A_P = R^T R in place (R in the upper triangle of A,
+// pitch W + 1), blocked right-looking with panels of NB rows.  Wavefront 0
+// factors a panel: rows j0 .. j0 + NB - 1 of R at columns l0 = j0 + lane and
+// l1 = j0 + 64 + lane (clamped to W - 1: a clamped lane repeats the work of
+// the lane that owns column W - 1) stay in registers; the entry (j, j) and
+// the row-j entries r_ju of the columns of later panel rows come from the
+// lanes that hold them (readlane), so the column loop makes no LDS access.
+// Every update is applied to all columns: below the diagonal (l < row) the
+// values are junk that the factorisation never reads (the caller zeroes the
+// strict lower triangle).  Then all threads subtract the panel's r_ji r_jl
+// (j in the panel, in order) from the trailing entries (i, l),
+// j0 + NB <= i <= l, in 4 x 4 blocks (each panel value loaded serves four
+// products; the blocks on the diagonal also write junk below it).  The
+// pivots d_j go to dsh (R's diagonal is sqrt(d_j)).  Wavefront 0 reports a
+// breakdown (d_j <= 0 or not a number) in *s_brk (zero on entry), which
+// every thread reads after the barrier: the result is the same everywhere.
+template <int W, int NT>
+__device__ bool pivot_cholesky(double *A, double *dsh, int *s_brk, int tid)
+{
+    constexpr int P = W + 1;
+    constexpr int NB = 16;
+    static_assert(W % NB == 0 && W <= 128, "two columns per lane");
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int j0 = 0; j0 < W; j0 += NB) {
+        if (wave == 0) {
+            const int l0 = min(j0 + lane, W - 1), l1 = min(j0 + 64 + lane, W - 1);
+            double p0[NB], p1[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                p0[u] = A[l0 * P + j0 + u];
+                p1[u] = A[l1 * P + j0 + u];
+            }
+            bool brk = false;
+#pragma unroll
+            for (int jj = 0; jj < NB; ++jj) {
+                const int j = j0 + jj;
+                const double dj = read_lane(p0[jj], jj);   // lane jj holds column j
+                // a breakdown (the same in every lane) voids the whole pivot:
+                // the panel runs on (on junk) so that the loop stays unrolled
+                brk = brk || !(dj > 0.0);
+                const double rinv = 1.0 / sqrt(dj);
+                if (lane == 0) dsh[j] = dj;
+                // row j of R at this lane's columns l > j (l = j keeps d_j)
+                const double s0 = p0[jj] * rinv, s1 = p1[jj] * rinv;
+                p0[jj] = (l0 > j) ? s0 : p0[jj];
+                p1[jj] = (l1 > j) ? s1 : p1[jj];
+                // the later rows of the panel: a_ul -= r_ju r_jl
+#pragma unroll
+                for (int u = jj + 1; u < NB; ++u) {
+                    const double rju = read_lane(p0[jj], u);   // lane u holds column j0 + u
+                    p0[u] -= rju * p0[jj];
+                    p1[u] -= rju * p1[jj];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                A[l0 * P + j0 + u] = p0[u];
+                A[l1 * P + j0 + u] = p1[u];
+            }
+            if (brk && lane == 0) *s_brk = 1;
+        }
+        __syncthreads();
+        if (*s_brk) return true;
+        const int t0 = j0 + NB;
+        const int nb4 = (W - t0) / 4;
+        for (int t = tid; t < nb4 * nb4; t += NT) {
+            const int bi = t % nb4, bl = t / nb4;
+            if (bi > bl) continue;
+            const int i0 = t0 + 4 * bi, c0 = t0 + 4 * bl;
+            double acc[4][4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[q][e] = A[(c0 + e) * P + i0 + q];
+#pragma unroll
+            for (int u0 = 0; u0 < NB; u0 += 4) {
+                double pi[4][4], pl[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        pi[q][k] = A[(i0 + q) * P + j0 + u0 + k];
+                        pl[q][k] = A[(c0 + q) * P + j0 + u0 + k];
+                    }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc[q][e] -= pi[q][k] * pl[e][k];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) A[(c0 + e) * P + i0 + q] = acc[q][e];
+        }
+        __syncthreads();
+    }
+    return false;
 }
 
 constexpr int kLogThreads = 256;
@@ -920,36 +1077,17 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
         s_bad = 0;
         s_brk = 0;
     }
-    // A_P, added up over the splits by k_gram_reduce (two halves of 32
-    // entries per thread in flight)
-    {
-        const double *src = a.ap + (size_t)pv * W * W;
-        constexpr int PER = W * W / kLogThreads / 2;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            double v[PER];
-#pragma unroll
-            for (int q = 0; q < PER; ++q) v[q] = src[tid + (h * PER + q) * kLogThreads];
-#pragma unroll
-            for (int q = 0; q < PER; ++q) {
-                const int e = tid + (h * PER + q) * kLogThreads;
-                A[(e / W) * P + (e % W)] = v[q];
-            }
-        }
-    }
+    // A_P, added up over the splits by k_gram_reduce
+    pivot_load_gram<W, kLogThreads>(a.ap + (size_t)pv * W * W, A, tid);
     __syncthreads();
-    // skip test; the square roots of the diagonal (in dsh until the
-    // Cholesky factorisation needs it) are taken once
+    // skip test; the square roots of the diagonal are taken once
     if (tid < W) dsh[tid] = sqrt(A[tid * P + tid]);
     __syncthreads();
-    for (int e = tid; e < W * W; e += kLogThreads) {
-        const int r = e % W, c = e / W;
-        const double x = A[c * P + r];
-        if (!isfinite(x)) s_bad = 1;
-        if (r < c && (a.all_pairs || (r < b && c >= b))) {
-            if (A[r * P + r] != 0.0 && A[c * P + c] != 0.0 && fabs(x) > a.tol * dsh[r] * dsh[c])
-                s_need = 1;
-        }
+    {
+        bool need, bad_entry;
+        pivot_skip_test<W, kLogThreads>(A, dsh, b, a.all_pairs != 0, a.tol, tid, need, bad_entry);
+        if (need) s_need = 1;
+        if (bad_entry) s_bad = 1;
     }
     __syncthreads();
     if (s_bad) {
@@ -963,83 +1101,7 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
         if (tid == 0) a.flag[pv] = 0;
         return;
     }
-    // Cholesky A_P = R^T R in place (R in the upper triangle), blocked
-    // right-looking with panels of NB rows: wavefront 0 factors a panel
-    // (rows j0 .. j0 + NB - 1 of R over all columns, each column's update of
-    // the later panel rows included; one wavefront's LDS accesses complete in
-    // order, so its columns need no barrier), then all threads subtract the
-    // panel's r_ji r_jl (j in the panel, in order) from the trailing entries
-    // (i, l), j0 + NB <= i <= l.  The pivots d_j go to dsh (R's diagonal is
-    // sqrt(d_j)).  Wavefront 0 reports a breakdown (d_j <= 0) in s_brk,
-    // which every thread reads after the barrier.
-    constexpr int NB = 16;
-    bool broke = false;
-    for (int j0 = 0; j0 < W; j0 += NB) {
-        if (wave == 0) {
-            // The panel rows j0 .. j0 + NB - 1 at columns l0 = j0 + lane and
-            // l1 = j0 + 64 + lane (clamped to W - 1: a clamped lane repeats
-            // the work of the lane that owns column W - 1) stay in registers
-            // while the panel is factored: the entry (j, j) and the row-j
-            // entries r_ju of the columns of later panel rows come from the
-            // lanes that hold them (readlane), so the column loop makes no
-            // LDS access.  Every update is applied to all columns: below the
-            // diagonal (l < row) the values are junk that the factorisation
-            // never reads, and the strict lower triangle is zeroed afterwards.
-            const int l0 = min(j0 + lane, W - 1), l1 = min(j0 + 64 + lane, W - 1);
-            double p0[NB], p1[NB];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                p0[u] = A[l0 * P + j0 + u];
-                p1[u] = A[l1 * P + j0 + u];
-            }
-            bool brk = false;
-#pragma unroll
-            for (int jj = 0; jj < NB; ++jj) {
-                const int j = j0 + jj;
-                const double dj = read_lane(p0[jj], jj);   // lane jj holds column j
-                // a breakdown (the same in every lane) voids the whole pivot:
-                // the panel runs on (on junk) so that the loop stays unrolled
-                brk = brk || !(dj > 0.0);
-                const double rjj = sqrt(dj);
-                if (lane == 0) dsh[j] = dj;
-                // row j of R at this lane's columns l > j (l = j keeps d_j)
-                const double s0 = p0[jj] / rjj, s1 = p1[jj] / rjj;
-                p0[jj] = (l0 > j) ? s0 : p0[jj];
-                p1[jj] = (l1 > j) ? s1 : p1[jj];
-                // the later rows of the panel: a_ul -= r_ju r_jl
-#pragma unroll
-                for (int u = jj + 1; u < NB; ++u) {
-                    const double rju = read_lane(p0[jj], u);   // lane u holds column j0 + u
-                    p0[u] -= rju * p0[jj];
-                    p1[u] -= rju * p1[jj];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                A[l0 * P + j0 + u] = p0[u];
-                A[l1 * P + j0 + u] = p1[u];
-            }
-            if (brk && lane == 0) s_brk = 1;
-        }
-        __syncthreads();
-        if (s_brk) {
-            broke = true;
-            break;
-        }
-        const int t0 = j0 + NB;
-        for (int l = t0 + (tid >> 4); l < W; l += kLogThreads / 16) {
-            double rl[NB];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) rl[u] = A[l * P + j0 + u];
-            for (int i = t0 + (tid & 15); i <= l; i += 16) {
-                double acc = A[l * P + i];
-#pragma unroll
-                for (int u = 0; u < NB; ++u) acc -= A[i * P + j0 + u] * rl[u];
-                A[l * P + i] = acc;
-            }
-        }
-        __syncthreads();
-    }
+    const bool broke = pivot_cholesky<W, kLogThreads>(A, dsh, &s_brk, tid);
     if (broke && !a.G) {
         // no FP64 copy of G to transform in place (the FP32 sweeps): the
         // pivot is left to the FP64 sweeps that follow
@@ -1105,7 +1167,7 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
                     }
                     double c, sn;
                     bool same, cl;
-                    const bool act = log_pair_transform<RPW, RB, NP>(
+                    const bool act = pair_transform<RPW, RB, NW, NP>(
                         xr, yr, red, wave, lane, a.tol, JP[lane] == JP[HB + cj], c, sn, same, bad, cl);
                     if (cl && wave == 0) ++ncl;
                     if (act) {
@@ -1144,7 +1206,7 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
                         }
                         double c, sn;
                         bool same, cl;
-                        const bool act = log_pair_transform<RPW, RB, NP>(
+                        const bool act = pair_transform<RPW, RB, NW, NP>(
                             xr, yr, red, wave, lane, a.tol, JP[pq.x] == JP[pq.y], c, sn, same, bad, cl);
                         if (cl && wave == 0) ++ncl;
                         if (wave == 0)
@@ -1291,6 +1353,184 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
     }
 }
 
+// ------------------------------------------------- k_pivot_solve_ij (W = 128)
+// The pivot solve of the block-oriented steps at W = 128 (b = 64): the one
+// inner sweep over the pairs (block I column, block J column) of Alg. 3.4,
+// in the bipartite shift order (step s pairs column k with column
+// b + (k + s) mod b).  Eight wavefronts; wavefront w keeps rows
+// [16 w, 16 w + 16) of R and of V_P in registers: lane k the block-I column
+// k and, at step s, the block-J column (k + s) mod b, which is the column
+// its pair rotates.  After each step every block-J column moves to the lane
+// below (a DPP rotate of the wavefront), the lane that pairs it next, so
+// the sweep makes no LDS access besides the partial dot products
+// (double-buffered: one barrier per step); after b steps each column is
+// back in its lane.  The rotation is applied without a branch (a pair that
+// does not rotate has c = 1, s = 0).  The load, skip test and Cholesky
+// factorisation are those of k_pivot_solve_log; after a breakdown V_P is
+// accumulated in LDS while the inner sweep runs on G_P.
+constexpr int kIJThreads = 512;
+// DPP control: wavefront rotate by one lane, lane k taking lane k + 1's value
+constexpr int kDppWaveRol1 = 0x134;
+
+template <int W>
+__global__ __launch_bounds__(kIJThreads) void k_pivot_solve_ij(PivotSolveArgs a)
+{
+    constexpr int NT = kIJThreads;
+    constexpr int NW = NT / 64;
+    constexpr int P = W + 1;
+    constexpr int HB = W / 2;          // b: pairs per step, one per lane
+    constexpr int NP = HB;
+    constexpr int RPW = W / NW;        // rows of R and V_P per wavefront
+    constexpr int RB = 8;              // rows summed as one pairwise subtree
+    static_assert(NP == 64 && RPW % RB == 0, "one lane per pair");
+    __shared__ double A[W * P];        // Gram, then R (upper); V_P after a breakdown
+    __shared__ double red[2][NW * 3 * NP];   // partial dots, by step parity
+    __shared__ double dsh[W];          // square roots of the diagonal, then the pivots d_j
+    __shared__ signed char JP[W];
+    __shared__ int s_need, s_bad, s_brk;
+    __shared__ unsigned long long s_rot[NW], s_cl[NW];
+    const int pv = blockIdx.x;
+    const int4 d = a.piv[pv];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int b = a.b;
+
+    if (tid < W) {
+        const int c = pivot_col(tid, d, b);
+        JP[tid] = (a.J && c >= 0) ? a.J[c] : (signed char)1;
+    }
+    if (tid == 0) {
+        s_need = 0;
+        s_bad = 0;
+        s_brk = 0;
+    }
+    pivot_load_gram<W, NT>(a.ap + (size_t)pv * W * W, A, tid);
+    __syncthreads();
+    if (tid < W) dsh[tid] = sqrt(A[tid * P + tid]);
+    __syncthreads();
+    {
+        bool need, bad_entry;
+        pivot_skip_test<W, NT>(A, dsh, b, false, a.tol, tid, need, bad_entry);
+        if (need) s_need = 1;
+        if (bad_entry) s_bad = 1;
+    }
+    __syncthreads();
+    if (s_bad) {
+        if (tid == 0) {
+            a.ctr->nonfinite = 1u;
+            a.flag[pv] = 0;
+        }
+        return;
+    }
+    if (!s_need) {
+        if (tid == 0) a.flag[pv] = 0;
+        return;
+    }
+    const bool broke = pivot_cholesky<W, NT>(A, dsh, &s_brk, tid);
+    if (broke && !a.G) {
+        // no FP64 copy of G to transform in place (the FP32 sweeps): the
+        // pivot is left to the FP64 sweeps that follow
+        if (tid == 0) {
+            atomicAdd(&a.ctr->breakdowns, 1ull);
+            a.flag[pv] = 0;
+        }
+        return;
+    }
+    unsigned long long rot = 0, ncl = 0;
+    int bad = 0;
+    const int r0 = wave * RPW;
+    double vx[RPW], vy[RPW];   // V_P's block-I column `lane`, block-J column in the lane
+    if (!broke) {
+        // R's columns `lane` and b + lane (diagonal sqrt(d_j), zero below it)
+        // and the same columns of V_P = I
+        double xr[RPW], yr[RPW];
+        const int ci = lane, cj = HB + lane;
+        const double di = sqrt(dsh[ci]), dj = sqrt(dsh[cj]);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+            const int row = r0 + r;
+            const double ai = A[ci * P + row], aj = A[cj * P + row];
+            xr[r] = row < ci ? ai : (row == ci ? di : 0.0);
+            yr[r] = row < cj ? aj : (row == cj ? dj : 0.0);
+            vx[r] = row == ci ? 1.0 : 0.0;
+            vy[r] = row == cj ? 1.0 : 0.0;
+        }
+        const signed char jpi = JP[ci];
+        for (int s = 0; s < HB; ++s) {
+            const bool same_sign = jpi == JP[HB + ((lane + s) & (HB - 1))];
+            double c, sn;
+            bool same, cl;
+            const bool act = pair_transform<RPW, RB, NW, NP>(xr, yr, red[s & 1], wave, lane, a.tol,
+                                                             same_sign, c, sn, same, bad, cl);
+            // x' = c x - s y (trigonometric) or c x + s y (hyperbolic), y' = s x + c y
+            const double sx = same ? -sn : sn;
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                const double x0 = xr[r], y0 = yr[r];
+                xr[r] = c * x0 + sx * y0;
+                yr[r] = sn * x0 + c * y0;
+                const double v0 = vx[r], w0 = vy[r];
+                vx[r] = c * v0 + sx * w0;
+                vy[r] = sn * v0 + c * w0;
+            }
+            if (wave == 0) {
+                rot += act ? 1ull : 0ull;
+                ncl += cl ? 1ull : 0ull;
+            }
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                yr[r] = dpp_move<kDppWaveRol1>(yr[r]);
+                vy[r] = dpp_move<kDppWaveRol1>(vy[r]);
+            }
+        }
+    } else {
+        // G_P is transformed in place; V_P (column-major, pitch P) collects
+        // the transforms for V
+        for (int e = tid; e < W * W; e += NT) {
+            const int r = e % W, c = e / W;
+            A[c * P + r] = (r == c) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        inner_sweep_global<NW>(a.G, a.ldg, a.m, A, P, W, JP, 0, W, a.tol, d, b, rot, ncl, &bad);
+    }
+    {
+        const double wr = wave_sum((double)rot), wc = wave_sum((double)ncl);
+        if (lane == 0) {
+            s_rot[wave] = (unsigned long long)wr;
+            s_cl[wave] = (unsigned long long)wc;
+        }
+    }
+    if (bad) s_bad = 1;
+    __syncthreads();
+    unsigned long long tot = 0, totc = 0;
+    for (int w = 0; w < NW; ++w) {
+        tot += s_rot[w];
+        totc += s_cl[w];
+    }
+    if (tid == 0) {
+        if (tot) atomicAdd(&a.ctr->rotations, tot);
+        if (totc) atomicAdd(&a.ctr->clamps, totc);
+        if (broke) atomicAdd(&a.ctr->breakdowns, 1ull);
+        if (s_bad) a.ctr->nonfinite = 1u;
+        a.flag[pv] = (tot > 0 && !s_bad) ? (broke ? 2 : 1) : 0;
+    }
+    if (tot > 0) {
+        // V_P row-major
+        double *out = a.vpt + (size_t)pv * W * W;
+        if (!broke) {
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                out[(size_t)(r0 + r) * W + lane] = vx[r];
+                out[(size_t)(r0 + r) * W + HB + lane] = vy[r];
+            }
+        } else {
+            for (int e = tid; e < W * W; e += NT) {
+                const int r = e / W, c = e % W;
+                out[e] = A[c * P + r];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- k_update
 // One workgroup (four wavefronts) handles consecutive 64-row tiles of one
 // pivot (of G, or of V): V_P is staged in LDS once, and the loads of tile
@@ -1375,27 +1615,37 @@ __device__ __forceinline__ void update_tiles(T *__restrict__ X, long ld, int row
     for (int t = 0; t < kUpdateTiles; ++t) {
         const int row = row0 + t * TR;
         if (!FULL && wrow + t * TR >= rows) break;   // wave-uniform
-        // no instruction: keeps the V_P reads of each tile in its tile (merged
-        // across the unrolled tiles they would hold many more registers)
-        asm volatile("" ::: "memory");
-        T nb[KS];
-        if (t + 1 < kUpdateTiles) {
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) nb[ks] = kload(ks, clamp_row(row + TR));
-        }
+        const bool more = t + 1 < kUpdateTiles;
+        const int nrow = clamp_row(row + TR);
         typename Mfma<T>::acc acc[NT];
 #pragma unroll
         for (int q = 0; q < NT; ++q) acc[q] = typename Mfma<T>::acc{0, 0, 0, 0};
-        // fully unrolled (a rolled k-loop indexes bf[] at run time); at
-        // W = 128 the V_P operands of four k-steps at a time (32 reads) are
-        // kept apart, else all 256 of a tile are read ahead into registers
+        // fully unrolled (a rolled k-loop indexes bf[] at run time).  The
+        // V_P operands go through two register sets: those of k-step ks + 1
+        // are read while the MFMAs of k-step ks run, and the empty asm
+        // statement (no instruction) keeps the reads of later k-steps from
+        // being hoisted further, where they would take many more registers.
+        // Once the MFMAs of k-step ks are issued, bf[ks] is reloaded with the
+        // next tile's operand (a whole tile ahead of its use), so one set of
+        // G operands is live, not two.
+        const T *sbase = S + lq * SP + (lane % 16);
+        T a_cur[NT], a_nxt[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) a_cur[q] = sbase[q * 16];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            if constexpr (W == 128)
-                if (ks % 4 == 0 && ks > 0) asm volatile("" ::: "memory");
-            const T *srow = S + (4 * ks + lq) * SP + (lane % 16);
+            if (ks + 1 < KS) {
 #pragma unroll
-            for (int q = 0; q < NT; ++q) acc[q] = mfma16x16x4(srow[q * 16], bf[ks], acc[q]);
+                for (int q = 0; q < NT; ++q) a_nxt[q] = sbase[4 * (ks + 1) * SP + q * 16];
+            }
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int q = 0; q < NT; ++q) acc[q] = mfma16x16x4(a_cur[q], bf[ks], acc[q]);
+            if (more) bf[ks] = kload(ks, nrow);
+            if (ks + 1 < KS) {
+#pragma unroll
+                for (int q = 0; q < NT; ++q) a_cur[q] = a_nxt[q];
+            }
         }
         if (FULL || row < rows) {
             // element r of tile q is pivot position q 16 + Mfma<T>::row(lane, r)
@@ -1414,10 +1664,6 @@ __device__ __forceinline__ void update_tiles(T *__restrict__ X, long ld, int row
                     char *cb = (char *)(X + (size_t)(in_i ? d.x : d.z) * ld) + (size_t)c0 * colb;
                     *(T *)(cb + lane_st) = acc[q][r];
                 }
-        }
-        if (t + 1 < kUpdateTiles) {
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) bf[ks] = nb[ks];
         }
     }
 }
@@ -1589,14 +1835,79 @@ static long log_entries(int W, bool full_block, int max_inner)
 // FP64 on the Gram partials; tol is the step's rotation threshold.  For
 // T = float there is no FP64 copy of G for the in-place breakdown path, so a
 // pivot whose Cholesky breaks down is left for the FP64 sweeps.
+// Launches the update of one step: rows of G (is_v false) or of V.
+template <int W, class T>
+static hipError_t launch_update(const BlockRunArgs &a, bool is_v, bool uneven, T *G, long ldg, T *V,
+                                long ldv, const int4 *piv, const double *vp, const int *flags,
+                                hipStream_t st)
+{
+    constexpr int GR = UpdateShape<W>::group_rows;
+    const int npiv = block_count(a.n, a.b) / 2;
+    // groups_g = 0 sends every workgroup of the launch to V
+    const int groups = is_v ? (a.n + GR - 1) / GR : (a.m + GR - 1) / GR;
+    const int groups_g = is_v ? 0 : groups;
+    const dim3 grid(groups, npiv);
+    if constexpr (W == 128) {
+        if (uneven)
+            k_update128<T, true><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, vp, flags,
+                                                       groups_g);
+        else
+            k_update128<T, false><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, vp, flags,
+                                                        groups_g);
+    } else {
+        if (uneven)
+            k_update<W, T, true><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, vp, flags,
+                                                       groups_g);
+        else
+            k_update<W, T, false><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, vp, flags,
+                                                        groups_g);
+    }
+    return hipGetLastError();
+}
+
+// V(:,P) <- V(:,P) V_P for the step whose pivots start at outer step k and
+// whose transforms sit in parity `par`, on the second stream, after the
+// solve's stream has recorded evReady; records evVdone[par].
+template <int W, class T>
+static hipError_t launch_v_update(BlockWorkspace *ws, const BlockRunArgs &a, BlockTables *t, int k,
+                                  int par, T *G, long ldg, T *V, long ldv)
+{
+    const int npiv = block_count(a.n, a.b) / 2;
+    const int4 *piv = t->d_outer + t->outer_start[k];
+    const double *vp = ws->vp + (size_t)par * npiv * W * W;
+    const int *flags = ws->flags + (size_t)par * npiv;
+    hipStream_t vs = ws->vstream;
+    hipError_t e;
+    if ((e = hipStreamWaitEvent(vs, ws->evReady, 0)) != hipSuccess) return e;
+    if ((e = a.timer->begin(vs, JEVD_K_UPDATE)) != hipSuccess) return e;
+    if ((e = launch_update<W, T>(a, true, !block_partition_even(a.n, a.b), G, ldg, V, ldv, piv, vp,
+                                 flags, vs)) != hipSuccess)
+        return e;
+    if ((e = a.timer->end(vs)) != hipSuccess) return e;
+    return hipEventRecord(ws->evVdone[par], vs);
+}
+
+// One parallel step of Alg. 3.4 (outer step k; its transforms V_P and flags
+// go to the buffer of parity `par`).  G is updated on the solve's stream.
+// V is read by no later step, so V's update is deferred: the update of the
+// previous step (outer step pend_k >= 0, parity par ^ 1) is released once
+// this step's Gram is formed and runs on the second stream beside this
+// step's pivot solve, which occupies one CU per pivot.  Before the pivot
+// solve overwrites a parity's buffer, the solve's stream waits for the V
+// update that last read it (wait_v).  On the last step of a sweep (last),
+// evReady is recorded after the pivot solve for the caller's flush of that
+// step's V update.
 template <int W, class T>
 static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTables *t, int k,
-                              int nsplit, int rows_per_split, SweepCounters *ctr, T *G, long ldg,
-                              T *V, long ldv, double tol)
+                              int par, bool wait_v, int pend_k, bool last, int nsplit,
+                              int rows_per_split, SweepCounters *ctr, T *G, long ldg, T *V,
+                              long ldv, double tol)
 {
     const int npiv = block_count(a.n, a.b) / 2;
     const int4 *piv = t->d_outer + t->outer_start[k];
     const bool uneven = !block_partition_even(a.n, a.b);
+    double *vp = ws->vp + (size_t)par * npiv * W * W;
+    int *flags = ws->flags + (size_t)par * npiv;
     hipStream_t st = a.stream;
     hipError_t e;
     if ((e = a.timer->begin(st, JEVD_K_GRAM)) != hipSuccess) return e;
@@ -1609,6 +1920,11 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
                                                                      ws->ap);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = a.timer->end(st)) != hipSuccess) return e;
+    if (pend_k >= 0) {
+        if ((e = hipEventRecord(ws->evReady, st)) != hipSuccess) return e;
+        if ((e = launch_v_update<W, T>(ws, a, t, pend_k, par ^ 1, G, ldg, V, ldv)) != hipSuccess)
+            return e;
+    }
 
     PivotSolveArgs p;
     p.ap = ws->ap;
@@ -1619,8 +1935,8 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     p.all_pairs = (a.full_block || k == 0) ? 1 : 0;
     p.full_block = a.full_block ? 1 : 0;
     p.max_inner = a.max_inner;
-    p.vpt = ws->vp;
-    p.flag = ws->flags;
+    p.vpt = vp;
+    p.flag = flags;
     p.ctr = ctr;
     p.G = (sizeof(T) == sizeof(double)) ? (double *)G : nullptr;
     p.m = a.m;
@@ -1628,35 +1944,21 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     p.sign_pivot = a.sign_pivot ? 1 : 0;
     p.vlog = ws->vlog;
     p.log_stride = log_entries(W, a.full_block, a.max_inner);
+    if (wait_v && (e = hipStreamWaitEvent(st, ws->evVdone[par], 0)) != hipSuccess) return e;
     if ((e = a.timer->begin(st, JEVD_K_PIVOT_SOLVE)) != hipSuccess) return e;
-    if constexpr (W == 128)
-        k_pivot_solve_log<128><<<npiv, kLogThreads, 0, st>>>(p);
-    else
+    if constexpr (W == 128) {
+        if (p.all_pairs)
+            k_pivot_solve_log<128><<<npiv, kLogThreads, 0, st>>>(p);
+        else
+            k_pivot_solve_ij<128><<<npiv, kIJThreads, 0, st>>>(p);
+    } else
         k_pivot_solve<W><<<npiv, kPivotThreads, pivot_lds_bytes(W), st>>>(p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = a.timer->end(st)) != hipSuccess) return e;
+    if (V && last && (e = hipEventRecord(ws->evReady, st)) != hipSuccess) return e;
 
-    constexpr int GR = UpdateShape<W>::group_rows;
-    const int groups_g = (a.m + GR - 1) / GR;
-    const int groups_v = V ? (a.n + GR - 1) / GR : 0;
-    const dim3 grid(groups_g + groups_v, npiv);
     if ((e = a.timer->begin(st, JEVD_K_UPDATE)) != hipSuccess) return e;
-    if constexpr (W == 128) {
-        if (uneven)
-            k_update128<T, true><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, ws->vp,
-                                                       ws->flags, groups_g);
-        else
-            k_update128<T, false><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, ws->vp,
-                                                        ws->flags, groups_g);
-    } else {
-        if (uneven)
-            k_update<W, T, true><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, ws->vp,
-                                                       ws->flags, groups_g);
-        else
-            k_update<W, T, false><<<grid, 256, 0, st>>>(G, a.m, ldg, V, a.n, ldv, piv, ws->vp,
-                                                        ws->flags, groups_g);
-    }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_update<W, T>(a, false, uneven, G, ldg, V, ldv, piv, vp, flags, st))) return e;
     return a.timer->end(st);
 }
 
@@ -1679,15 +1981,23 @@ static int prepare_steps(BlockWorkspace *ws, const BlockRunArgs &a, int *nsplit_
     nsplit = (a.m + rows_per_split - 1) / rows_per_split;
     rc = grow(&ws->partial, &ws->capPartial, (size_t)npiv * nsplit * W * W);
     if (rc) return rc;
-    rc = grow(&ws->vp, &ws->capVp, (size_t)npiv * W * W);
+    rc = grow(&ws->vp, &ws->capVp, (size_t)2 * npiv * W * W);   // two parities
     if (rc) return rc;
     rc = grow(&ws->ap, &ws->capAp, (size_t)npiv * W * W);
     if (rc) return rc;
-    rc = grow(&ws->flags, &ws->capFlags, (size_t)npiv);
+    rc = grow(&ws->flags, &ws->capFlags, (size_t)2 * npiv);
     if (rc) return rc;
     if (W == 128) {
         rc = grow(&ws->vlog, &ws->capVlog, (size_t)npiv * log_entries(W, a.full_block, a.max_inner));
         if (rc) return rc;
+    }
+    if (a.V && !ws->vstream) {
+        // default priority, like the solve's stream
+        HIP_TRY(hipStreamCreateWithFlags(&ws->vstream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&ws->evReady, hipEventDisableTiming));
+        for (int i = 0; i < 2; ++i)
+            HIP_TRY(hipEventCreateWithFlags(&ws->evVdone[i], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&ws->evJoin, hipEventDisableTiming));
     }
     if (W == 64)
         HIP_TRY(hipFuncSetAttribute((const void *)k_pivot_solve<64>,
@@ -1715,17 +2025,50 @@ static int block_sweeps(BlockWorkspace *ws, const BlockRunArgs &a, T *G, long ld
     BlockTables *t = tables_of(ws);
     const int N = block_count(a.n, a.b);
     HIP_TRY(hipMemsetAsync(dctr, 0, sizeof(SweepCounters) * max_sweeps, a.stream));
+    // the second stream starts after what the solve's stream holds (V's
+    // initial value) and is joined back into it at the end of every sweep
+    const bool split = V != nullptr;
+    if (split) {
+        HIP_TRY(hipEventRecord(ws->evJoin, a.stream));
+        HIP_TRY(hipStreamWaitEvent(ws->vstream, ws->evJoin, 0));
+    }
+    int step = 0;
     for (int s = 0; s < max_sweeps; ++s) {
-        for (int k = 0; k < N; ++k) {
-            hipError_t e;
+        hipError_t e = hipSuccess;
+        int pend_k = -1;   // outer step whose V update is not yet enqueued
+        for (int k = 0; k < N && e == hipSuccess; ++k, ++step) {
+            const int par = step & 1;
+            const bool wait_v = split && step >= 2;
             if (a.b == 16)
-                e = launch_step<32, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol);
+                e = launch_step<32, T>(ws, a, t, k, par, wait_v, pend_k, k == N - 1, nsplit,
+                                        rows_per_split, dctr + s, G, ldg, V, ldv, tol);
             else if (a.b == 32)
-                e = launch_step<64, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol);
+                e = launch_step<64, T>(ws, a, t, k, par, wait_v, pend_k, k == N - 1, nsplit,
+                                        rows_per_split, dctr + s, G, ldg, V, ldv, tol);
             else
-                e = launch_step<128, T>(ws, a, t, k, nsplit, rows_per_split, dctr + s, G, ldg, V, ldv, tol);
-            HIP_TRY(e);
+                e = launch_step<128, T>(ws, a, t, k, par, wait_v, pend_k, k == N - 1, nsplit,
+                                        rows_per_split, dctr + s, G, ldg, V, ldv, tol);
+            pend_k = split ? k : -1;
         }
+        if (split) {
+            if (e == hipSuccess && pend_k >= 0) {
+                const int par = (step - 1) & 1;
+                if (a.b == 16)
+                    e = launch_v_update<32, T>(ws, a, t, pend_k, par, G, ldg, V, ldv);
+                else if (a.b == 32)
+                    e = launch_v_update<64, T>(ws, a, t, pend_k, par, G, ldg, V, ldv);
+                else
+                    e = launch_v_update<128, T>(ws, a, t, pend_k, par, G, ldg, V, ldv);
+            }
+            // also after a failed launch: nothing may still run on V at return
+            hipError_t j = hipEventRecord(ws->evJoin, ws->vstream);
+            if (j == hipSuccess) j = hipStreamWaitEvent(a.stream, ws->evJoin, 0);
+            if (j != hipSuccess) {
+                (void)hipStreamSynchronize(ws->vstream);
+                if (e == hipSuccess) e = j;
+            }
+        }
+        HIP_TRY(e);
         HIP_TRY(hipMemcpyAsync(hctr + s, dctr + s, sizeof(SweepCounters), hipMemcpyDeviceToHost,
                                a.stream));
         HIP_TRY(hipStreamSynchronize(a.stream));
@@ -1869,6 +2212,13 @@ void block_workspace_free(BlockWorkspace *ws)
     if (ws->v32) (void)hipFree(ws->v32);
     if (ws->t64) (void)hipFree(ws->t64);
     if (ws->w64) (void)hipFree(ws->w64);
+    if (ws->vstream) {
+        (void)hipStreamSynchronize(ws->vstream);
+        (void)hipStreamDestroy(ws->vstream);
+        (void)hipEventDestroy(ws->evReady);
+        for (int i = 0; i < 2; ++i) (void)hipEventDestroy(ws->evVdone[i]);
+        (void)hipEventDestroy(ws->evJoin);
+    }
     if (ws->tables) {
         BlockTables *t = (BlockTables *)ws->tables;
         if (t->d_outer) (void)hipFree(t->d_outer);
