@@ -96,3 +96,9 @@ def test_committed_golden_records_are_complete():
         assert lam.shape == (meta["n"],) and np.all(np.isfinite(lam))
         assert len(meta["input_sha256"]) == 64 and meta["status"] == 0
         assert meta["command"].startswith("python tests/golden/make_block_golden.py")
+        if "truth" in meta:
+            # the high-precision solve of the same input, for the gate's (1.2) fallback
+            lam80 = np.load(path[:-len(".json")] + ".lam80.npy", allow_pickle=False)
+            assert lam80.shape == (meta["n"],) and np.all(np.isfinite(lam80))
+            assert meta["truth"]["command"].startswith("python tests/golden/make_block_golden.py --truth")
+            assert meta["kappa_colscaled"] >= 1.0
