@@ -734,7 +734,9 @@ def main():
 
     cpu = None
     gate = None
-    if not args.no_cpu_baseline:
+    # block workloads: the gate uses the cached oracle solve, so it runs with
+    # --no-cpu-baseline too (which then skips only the CPU timing)
+    if not args.no_cpu_baseline or block:
         from oracle import oracle as O
         from oracle import gates
         model, ncpu = host_cpu()
@@ -774,6 +776,7 @@ def main():
                     cres = gates.eig_gate(wl.G, compare["lam"], lam_ref, truth,
                                           meta.get("kappa_colscaled"))
                     compare["accuracy"] = cres
+        if block and not args.no_cpu_baseline:
             # the threaded oracle (the disjoint pivots of each step on all host
             # cores; bit for bit the sequential oracle) timed on the first
             # steps of a sweep: more steps until ~15 s of CPU work

@@ -288,6 +288,143 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     gram_body<128, T>(G, m, ldg, piv, rows_per_split, partial);
 }
 
+// The Gram of the W = 128 pivots without LDS staging.  Wavefront w owns
+// half h = w % 2 of the 36 upper tiles (18 each) and takes the chunks of 8
+// rows c = w / 2, w / 2 + 2, ... of the split, so there is no barrier in the
+// row loop.  The operands come straight from G: for column block c a lane
+// holds column c 16 + lane % 16 at rows 2 g and 2 g + 1 of the chunk,
+// g = lane / 16, read as one 16-byte load (the 64 lanes of a block cover its
+// 16 columns x 8 rows).  The chunk's two k-steps take the first and the
+// second element of each pair: the Gram sums over the rows, so which row
+// feeds which k-slot of an MFMA only has to be the same for both operands.
+// Four register sets rotate, the operands of the next three chunks in
+// flight while a chunk's MFMAs run.  At the end the two row halves of each
+// tile half are added in LDS (in a fixed order).  For even partitions (no
+// empty position) and an even ldg (16-byte aligned row pairs); the last
+// chunk of a split may be partial (rows past r_end are zero).
+constexpr int kGramRowsChunk = 8;
+
+__device__ __forceinline__ void gram_rows_load(const char *const *colb, unsigned off, double2 *o)
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) o[c] = *(const double2 *)(colb[c] + off);
+}
+
+// Row and column of upper tile T of 8 x 8 tiles, as compile-time constants.
+template <int T> struct UpperTile8 {
+    static constexpr int i = upper_tile_i(8, T);
+    static constexpr int j = upper_tile_j(8, T);
+};
+
+template <int H, size_t... Q>
+__device__ __forceinline__ void gram_rows_mfmas(const double *op, d4 *acc, std::index_sequence<Q...>)
+{
+    ((acc[Q] = mfma16x16x4(op[UpperTile8<18 * H + (int)Q>::i], op[UpperTile8<18 * H + (int)Q>::j],
+                           acc[Q])),
+     ...);
+}
+
+template <int H>
+__device__ __forceinline__ void gram_rows_chunk(const double2 *o, d4 *acc)
+{
+    double op[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) op[c] = o[c].x;
+    gram_rows_mfmas<H>(op, acc, std::make_index_sequence<18>());
+#pragma unroll
+    for (int c = 0; c < 8; ++c) op[c] = o[c].y;
+    gram_rows_mfmas<H>(op, acc, std::make_index_sequence<18>());
+}
+
+// The row loop of one wavefront over the chunks c0, c0 + 2, ... (n of
+// them); off: the byte offset of this lane's first row pair.  Chunk j + 3
+// is loaded into the set chunk j - 1 used.  The main loop takes four chunks
+// per pass without a branch (so that the count of loads in flight is the
+// same on every path and the waits stay exact); the last n mod 4 chunks
+// follow.  Loads past the last chunk reload it (in bounds, never used).
+template <int H>
+__device__ __forceinline__ void gram_rows_loop(const char *const *colb, unsigned off, int n, d4 *acc)
+{
+    constexpr unsigned step = 2 * kGramRowsChunk * sizeof(double);   // to the wavefront's next chunk
+    double2 b0[8], b1[8], b2[8], b3[8];
+    auto at = [&](int j) { return off + (unsigned)min(j, n - 1) * step; };
+    gram_rows_load(colb, at(0), b0);
+    gram_rows_load(colb, at(1), b1);
+    gram_rows_load(colb, at(2), b2);
+    int j = 0;
+    for (; j + 4 <= n; j += 4) {
+        gram_rows_load(colb, at(j + 3), b3);
+        gram_rows_chunk<H>(b0, acc);
+        gram_rows_load(colb, at(j + 4), b0);
+        gram_rows_chunk<H>(b1, acc);
+        gram_rows_load(colb, at(j + 5), b1);
+        gram_rows_chunk<H>(b2, acc);
+        gram_rows_load(colb, at(j + 6), b2);
+        gram_rows_chunk<H>(b3, acc);
+    }
+    const int rem = n - j;   // chunks j, j + 1, j + 2 are in b0, b1, b2
+    if (rem > 0) gram_rows_chunk<H>(b0, acc);
+    if (rem > 1) gram_rows_chunk<H>(b1, acc);
+    if (rem > 2) gram_rows_chunk<H>(b2, acc);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_gram128_rows(
+    const double *__restrict__ G, int m, long ldg, const int4 *__restrict__ piv, int rows_per_split,
+    double *__restrict__ partial)
+{
+    constexpr int W = 128, NT = 8, NH = 18;
+    __shared__ double red[2 * NH * 256];   // the tiles of wavefronts 2 and 3, element-major
+    const int pv = blockIdx.x, split = blockIdx.y;
+    const int4 d = piv[pv];
+    const int lane = threadIdx.x & 63, g = lane / 16;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int half = wave & 1, c0 = wave >> 1;
+    const int r_begin = split * rows_per_split;
+    const int r_end = min(m, r_begin + rows_per_split);
+    // block c: uniform first column (of block I for c < 4, of block J after)
+    // at the split's first row; this lane's column lane % 16 of it and its
+    // row pair in chunk c0 as a byte offset
+    const char *colb[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c)
+        colb[c] = (const char *)(G + (size_t)(c < 4 ? d.x + 16 * c : d.z + 16 * (c - 4)) * ldg + r_begin);
+    const unsigned off = ((unsigned)(lane % 16) * (unsigned)ldg + (unsigned)(kGramRowsChunk * c0 + 2 * g)) *
+                         (unsigned)sizeof(double);
+    d4 acc[NH];
+#pragma unroll
+    for (int q = 0; q < NH; ++q) acc[q] = d4{0, 0, 0, 0};
+    const int nchunks = (r_end - r_begin) / kGramRowsChunk;   // all full (8 | m, 8 | rows_per_split)
+    const int n = (nchunks - c0 + 1) / 2;                     // chunks of this wavefront
+    if (n > 0) {
+        if (half == 0)
+            gram_rows_loop<0>(colb, off, n, acc);
+        else
+            gram_rows_loop<1>(colb, off, n, acc);
+    }
+    // the second row half (wavefronts 2, 3) to LDS, added by the first (0, 1)
+    double *rh = red + half * NH * 256;
+    if (c0 == 1) {
+#pragma unroll
+        for (int q = 0; q < NH; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) rh[q * 256 + r * 64 + lane] = acc[q][r];
+    }
+    __syncthreads();
+    if (c0 == 0) {
+        double *out = partial + ((size_t)pv * gridDim.y + split) * W * W;
+#pragma unroll
+        for (int q = 0; q < NH; ++q) {
+            const int t = NH * half + q;
+            const int ti = upper_tile_i(NT, t), tj = upper_tile_j(NT, t);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = ti * 16 + Mfma<double>::row(lane, r), col = tj * 16 + lane % 16;
+                out[(size_t)col * W + row] = acc[q][r] + rh[q * 256 + r * 64 + lane];
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------- k_gram_reduce
 // Adds the split-K partial Grams of every pivot in split order (the same
 // order for every entry, so the sum is deterministic) and writes the full
@@ -828,16 +965,38 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
 // wavefront, so all get the same totals.  Returns whether the pair rotates;
 // c, sn, and same (trigonometric) then hold the transform (else c = 1,
 // sn = 0).
+// RB = 0: the rows are summed in four interleaved chains (rows r mod 4),
+// added pairwise, which holds 12 partial sums where the subtrees hold 36.
 template <int RPW, int RB, int NW, int NP>
 __device__ __forceinline__ bool pair_transform(const double *xr, const double *yr, double *red,
                                                int wave, int lane, double tol, bool same_sign,
                                                double &c, double &sn, bool &same, int &bad,
                                                bool &clamped)
 {
-    double pxx[RPW / RB], pyy[RPW / RB], pxy[RPW / RB];
+    constexpr int NG = RB > 0 ? RPW / RB : 1;
+    double pxx[NG], pyy[NG], pxy[NG];
+    if constexpr (RB == 0) {
+        double axx[4], ayy[4], axy[4];
 #pragma unroll
-    for (int g = 0; g < RPW / RB; ++g) {
-        double sxx[RB], syy[RB], sxy[RB];
+        for (int k = 0; k < 4; ++k) {
+            axx[k] = xr[k] * xr[k];
+            ayy[k] = yr[k] * yr[k];
+            axy[k] = xr[k] * yr[k];
+        }
+#pragma unroll
+        for (int r = 4; r < RPW; ++r) {
+            axx[r % 4] = fma(xr[r], xr[r], axx[r % 4]);
+            ayy[r % 4] = fma(yr[r], yr[r], ayy[r % 4]);
+            axy[r % 4] = fma(xr[r], yr[r], axy[r % 4]);
+        }
+        pxx[0] = (axx[0] + axx[1]) + (axx[2] + axx[3]);
+        pyy[0] = (ayy[0] + ayy[1]) + (ayy[2] + ayy[3]);
+        pxy[0] = (axy[0] + axy[1]) + (axy[2] + axy[3]);
+    }
+#pragma unroll
+    for (int g = 0; g < (RB > 0 ? RPW / RB : 0); ++g) {
+        constexpr int RS = RB > 0 ? RB : 1;
+        double sxx[RS], syy[RS], sxy[RS];
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const double x = xr[g * RB + r], y = yr[g * RB + r];
@@ -858,7 +1017,7 @@ __device__ __forceinline__ bool pair_transform(const double *xr, const double *y
         pxy[g] = sxy[0];
     }
 #pragma unroll
-    for (int h = RPW / RB / 2; h > 0; h /= 2)
+    for (int h = NG / 2; h > 0; h /= 2)
 #pragma unroll
         for (int g = 0; g < h; ++g) {
             pxx[g] += pxx[g + h];
@@ -1357,17 +1516,20 @@ __global__ __launch_bounds__(kLogThreads) void k_pivot_solve_log(PivotSolveArgs 
 // The pivot solve of the block-oriented steps at W = 128 (b = 64): the one
 // inner sweep over the pairs (block I column, block J column) of Alg. 3.4,
 // in the bipartite shift order (step s pairs column k with column
-// b + (k + s) mod b).  Eight wavefronts; wavefront w keeps rows
-// [16 w, 16 w + 16) of R and of V_P in registers: lane k the block-I column
-// k and, at step s, the block-J column (k + s) mod b, which is the column
-// its pair rotates.  After each step every block-J column moves to the lane
-// below (a DPP rotate of the wavefront), the lane that pairs it next, so
-// the sweep makes no LDS access besides the partial dot products
-// (double-buffered: one barrier per step); after b steps each column is
-// back in its lane.  The rotation is applied without a branch (a pair that
-// does not rotate has c = 1, s = 0).  The load, skip test and Cholesky
-// factorisation are those of k_pivot_solve_log; after a breakdown V_P is
-// accumulated in LDS while the inner sweep runs on G_P.
+// b + (k + s) mod b).  Eight wavefronts in two roles.  Wavefronts 0-3 keep
+// rows [32 w, 32 w + 32) of R in registers: lane k the block-I column k and,
+// at step s, the block-J column (k + s) mod b, which is the column its pair
+// rotates; they form the dot products (partials meet in LDS, double-buffered
+// by step parity: one barrier per step), the transforms, and rotate R.
+// Wavefronts 4-7 keep the same rows of V_P and apply each step's transforms
+// one step later, from the (c, s) that wavefront 0 leaves in LDS, while the
+// R wavefronts wait on their reductions.  After each step every block-J
+// column moves to the lane below (a DPP rotate of the wavefront), the lane
+// that pairs it next; after b steps each column is back in its lane.  The
+// rotation is applied without a branch (a pair that does not rotate has
+// c = 1, s = 0).  The load, skip test and Cholesky factorisation are those
+// of k_pivot_solve_log; after a breakdown V_P is accumulated in LDS while
+// the inner sweep runs on G_P.
 constexpr int kIJThreads = 512;
 // DPP control: wavefront rotate by one lane, lane k taking lane k + 1's value
 constexpr int kDppWaveRol1 = 0x134;
@@ -1380,18 +1542,21 @@ __global__ __launch_bounds__(kIJThreads) void k_pivot_solve_ij(PivotSolveArgs a)
     constexpr int P = W + 1;
     constexpr int HB = W / 2;          // b: pairs per step, one per lane
     constexpr int NP = HB;
-    constexpr int RPW = W / NW;        // rows of R and V_P per wavefront
-    constexpr int RB = 8;              // rows summed as one pairwise subtree
-    static_assert(NP == 64 && RPW % RB == 0, "one lane per pair");
+    constexpr int NR = NW / 2;         // wavefronts per role
+    constexpr int RPW = W / NR;        // rows of R (or of V_P) per wavefront
+    constexpr int RB = 0;              // dot products in four interleaved chains
+    static_assert(NP == 64 && RPW % 4 == 0, "one lane per pair");
     __shared__ double A[W * P];        // Gram, then R (upper); V_P after a breakdown
-    __shared__ double red[2][NW * 3 * NP];   // partial dots, by step parity
+    __shared__ double red[2][NR * 3 * NP];   // partial dots, by step parity
+    __shared__ double cs[2][3 * NP];         // c, s and the signed s of each pair, by step parity
     __shared__ double dsh[W];          // square roots of the diagonal, then the pivots d_j
     __shared__ signed char JP[W];
     __shared__ int s_need, s_bad, s_brk;
     __shared__ unsigned long long s_rot[NW], s_cl[NW];
     const int pv = blockIdx.x;
     const int4 d = a.piv[pv];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int b = a.b;
 
     if (tid < W) {
@@ -1437,49 +1602,77 @@ __global__ __launch_bounds__(kIJThreads) void k_pivot_solve_ij(PivotSolveArgs a)
     }
     unsigned long long rot = 0, ncl = 0;
     int bad = 0;
-    const int r0 = wave * RPW;
-    double vx[RPW], vy[RPW];   // V_P's block-I column `lane`, block-J column in the lane
+    const bool rwave = wave < NR;
+    const int r0 = (wave % NR) * RPW;
+    double *out = a.vpt + (size_t)pv * W * W;
     if (!broke) {
-        // R's columns `lane` and b + lane (diagonal sqrt(d_j), zero below it)
-        // and the same columns of V_P = I
-        double xr[RPW], yr[RPW];
         const int ci = lane, cj = HB + lane;
-        const double di = sqrt(dsh[ci]), dj = sqrt(dsh[cj]);
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-            const int row = r0 + r;
-            const double ai = A[ci * P + row], aj = A[cj * P + row];
-            xr[r] = row < ci ? ai : (row == ci ? di : 0.0);
-            yr[r] = row < cj ? aj : (row == cj ? dj : 0.0);
-            vx[r] = row == ci ? 1.0 : 0.0;
-            vy[r] = row == cj ? 1.0 : 0.0;
-        }
         const signed char jpi = JP[ci];
-        for (int s = 0; s < HB; ++s) {
-            const bool same_sign = jpi == JP[HB + ((lane + s) & (HB - 1))];
-            double c, sn;
-            bool same, cl;
-            const bool act = pair_transform<RPW, RB, NW, NP>(xr, yr, red[s & 1], wave, lane, a.tol,
-                                                             same_sign, c, sn, same, bad, cl);
-            // x' = c x - s y (trigonometric) or c x + s y (hyperbolic), y' = s x + c y
-            const double sx = same ? -sn : sn;
+        if (rwave) {
+            // R's block-I column `lane` and the block-J column in the lane
+            // (the diagonal sqrt(d_j), zero below it)
+            double xr[RPW], yr[RPW];
+            const double di = sqrt(dsh[ci]), dj = sqrt(dsh[cj]);
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
-                const double x0 = xr[r], y0 = yr[r];
-                xr[r] = c * x0 + sx * y0;
-                yr[r] = sn * x0 + c * y0;
-                const double v0 = vx[r], w0 = vy[r];
-                vx[r] = c * v0 + sx * w0;
-                vy[r] = sn * v0 + c * w0;
+                const int row = r0 + r;
+                const double ai = A[ci * P + row], aj = A[cj * P + row];
+                xr[r] = row < ci ? ai : (row == ci ? di : 0.0);
+                yr[r] = row < cj ? aj : (row == cj ? dj : 0.0);
             }
-            if (wave == 0) {
-                rot += act ? 1ull : 0ull;
-                ncl += cl ? 1ull : 0ull;
+            for (int s = 0; s < HB; ++s) {
+                const bool same_sign = jpi == JP[HB + ((lane + s) & (HB - 1))];
+                double c, sn;
+                bool same, cl;
+                const bool act = pair_transform<RPW, RB, NR, NP>(xr, yr, red[s & 1], wave, lane, a.tol,
+                                                                 same_sign, c, sn, same, bad, cl);
+                // x' = c x - s y (trigonometric) or c x + s y (hyperbolic), y' = s x + c y
+                const double sx = same ? -sn : sn;
+                if (wave == 0) {
+                    cs[s & 1][lane] = c;
+                    cs[s & 1][NP + lane] = sn;
+                    cs[s & 1][2 * NP + lane] = sx;
+                    rot += act ? 1ull : 0ull;
+                    ncl += cl ? 1ull : 0ull;
+                }
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    const double x0 = xr[r], y0 = yr[r];
+                    xr[r] = c * x0 + sx * y0;
+                    yr[r] = sn * x0 + c * y0;
+                }
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) yr[r] = dpp_move<kDppWaveRol1>(yr[r]);
             }
+            __syncthreads();   // pairs with the V wavefronts' last pass
+        } else {
+            // V_P's columns `lane` and b + lane of I; pass s applies step
+            // s - 1 (one barrier per pass, as the R wavefronts' steps)
+            double vx[RPW], vy[RPW];
 #pragma unroll
             for (int r = 0; r < RPW; ++r) {
-                yr[r] = dpp_move<kDppWaveRol1>(yr[r]);
-                vy[r] = dpp_move<kDppWaveRol1>(vy[r]);
+                vx[r] = r0 + r == ci ? 1.0 : 0.0;
+                vy[r] = r0 + r == cj ? 1.0 : 0.0;
+            }
+            for (int s = 0; s <= HB; ++s) {
+                __syncthreads();
+                if (s == 0) continue;
+                const double *e = cs[(s - 1) & 1];
+                const double c = e[lane], sn = e[NP + lane], sx = e[2 * NP + lane];
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) {
+                    const double x0 = vx[r], y0 = vy[r];
+                    vx[r] = c * x0 + sx * y0;
+                    vy[r] = sn * x0 + c * y0;
+                }
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) vy[r] = dpp_move<kDppWaveRol1>(vy[r]);
+            }
+            // V_P row-major (the update reads it only if a pair rotated)
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) {
+                out[(size_t)(r0 + r) * W + lane] = vx[r];
+                out[(size_t)(r0 + r) * W + HB + lane] = vy[r];
             }
         }
     } else {
@@ -1513,20 +1706,11 @@ __global__ __launch_bounds__(kIJThreads) void k_pivot_solve_ij(PivotSolveArgs a)
         if (s_bad) a.ctr->nonfinite = 1u;
         a.flag[pv] = (tot > 0 && !s_bad) ? (broke ? 2 : 1) : 0;
     }
-    if (tot > 0) {
-        // V_P row-major
-        double *out = a.vpt + (size_t)pv * W * W;
-        if (!broke) {
-#pragma unroll
-            for (int r = 0; r < RPW; ++r) {
-                out[(size_t)(r0 + r) * W + lane] = vx[r];
-                out[(size_t)(r0 + r) * W + HB + lane] = vy[r];
-            }
-        } else {
-            for (int e = tid; e < W * W; e += NT) {
-                const int r = e / W, c = e % W;
-                out[e] = A[c * P + r];
-            }
+    if (tot > 0 && broke) {
+        // V_P row-major from the LDS copy
+        for (int e = tid; e < W * W; e += NT) {
+            const int r = e / W, c = e % W;
+            out[e] = A[c * P + r];
         }
     }
 }
@@ -1900,8 +2084,8 @@ static hipError_t launch_v_update(BlockWorkspace *ws, const BlockRunArgs &a, Blo
 template <int W, class T>
 static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTables *t, int k,
                               int par, bool wait_v, int pend_k, bool last, int nsplit,
-                              int rows_per_split, SweepCounters *ctr, T *G, long ldg, T *V,
-                              long ldv, double tol)
+                              int rows_per_split, bool gram_rows, SweepCounters *ctr, T *G,
+                              long ldg, T *V, long ldv, double tol)
 {
     const int npiv = block_count(a.n, a.b) / 2;
     const int4 *piv = t->d_outer + t->outer_start[k];
@@ -1911,9 +2095,19 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
     hipStream_t st = a.stream;
     hipError_t e;
     if ((e = a.timer->begin(st, JEVD_K_GRAM)) != hipSuccess) return e;
-    if constexpr (W == 128)
-        k_gram128<T><<<dim3(npiv, nsplit), 256, 0, st>>>(G, a.m, ldg, piv, rows_per_split, ws->partial);
-    else
+    if constexpr (W == 128) {
+        if constexpr (sizeof(T) == sizeof(double)) {
+            if (gram_rows)
+                k_gram128_rows<<<dim3(npiv, nsplit), 256, 0, st>>>((const double *)G, a.m, ldg, piv,
+                                                                   rows_per_split, ws->partial);
+            else
+                k_gram128<T><<<dim3(npiv, nsplit), 256, 0, st>>>(G, a.m, ldg, piv, rows_per_split,
+                                                                 ws->partial);
+        } else {
+            k_gram128<T><<<dim3(npiv, nsplit), 256, 0, st>>>(G, a.m, ldg, piv, rows_per_split,
+                                                             ws->partial);
+        }
+    } else
         k_gram<W, T><<<dim3(npiv, nsplit), 256, 0, st>>>(G, a.m, ldg, piv, rows_per_split, ws->partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_gram_reduce<W><<<dim3((W * W + 255) / 256, npiv), 256, 0, st>>>(ws->partial, nsplit, piv, a.b,
@@ -1965,20 +2159,40 @@ static hipError_t launch_step(BlockWorkspace *ws, const BlockRunArgs &a, BlockTa
 // Row split of the pivot Grams (about 1024 workgroups per step for W <= 64,
 // 512 for W = 128, whose workgroups are twice as long) and the step
 // workspaces; sets the pivot solve's LDS limit.
-static int prepare_steps(BlockWorkspace *ws, const BlockRunArgs &a, int *nsplit_out,
-                         int *rows_per_split_out)
+// Whether the Gram of the FP64 sweeps at W = 128 takes k_gram128_rows: an
+// even partition, row pairs 16-byte aligned (even ldg), whole chunks of 8
+// rows, and the lane offsets within 32 bits.
+static bool gram_rows_applies(const BlockRunArgs &a, long ldg, bool fp64)
+{
+    return fp64 && a.b == 64 && block_partition_even(a.n, a.b) && ldg % 2 == 0 && a.m % 8 == 0 &&
+           (ldg + a.m) * 16 * (long)sizeof(double) < (1L << 31);
+}
+
+static int prepare_steps(BlockWorkspace *ws, const BlockRunArgs &a, long ldg, bool fp64,
+                         int *nsplit_out, int *rows_per_split_out, bool *gram_rows_out)
 {
     const int b = a.b, W = 2 * b, npiv = block_count(a.n, b) / 2;
     int rc = prepare_tables(ws, a.n, b, a.stream);
     if (rc) return rc;
-    const int target = (W == 128) ? 512 : 1024;
-    int nsplit = target / npiv;
-    if (nsplit < 1) nsplit = 1;
-    int maxsplit = (a.m + 255) / 256;
-    if (nsplit > maxsplit) nsplit = maxsplit;
-    int rows_per_split = (a.m + nsplit - 1) / nsplit;
-    rows_per_split = (rows_per_split + 31) / 32 * 32;
+    const bool gram_rows = gram_rows_applies(a, ldg, fp64);
+    int nsplit, rows_per_split;
+    if (gram_rows) {
+        // one workgroup per CU (it holds the whole register file), at least
+        // 64 rows per split
+        nsplit = std::max(1, std::min(256 / npiv, a.m / 64));
+        rows_per_split = (a.m + nsplit - 1) / nsplit;
+        rows_per_split = (rows_per_split + 7) / 8 * 8;
+    } else {
+        const int target = (W == 128) ? 512 : 1024;
+        nsplit = target / npiv;
+        if (nsplit < 1) nsplit = 1;
+        int maxsplit = (a.m + 255) / 256;
+        if (nsplit > maxsplit) nsplit = maxsplit;
+        rows_per_split = (a.m + nsplit - 1) / nsplit;
+        rows_per_split = (rows_per_split + 31) / 32 * 32;
+    }
     nsplit = (a.m + rows_per_split - 1) / rows_per_split;
+    *gram_rows_out = gram_rows;
     rc = grow(&ws->partial, &ws->capPartial, (size_t)npiv * nsplit * W * W);
     if (rc) return rc;
     rc = grow(&ws->vp, &ws->capVp, (size_t)2 * npiv * W * W);   // two parities
@@ -2020,7 +2234,9 @@ static int block_sweeps(BlockWorkspace *ws, const BlockRunArgs &a, T *G, long ld
 {
     *sweeps_done = 0;
     int nsplit = 0, rows_per_split = 0;
-    int rc = prepare_steps(ws, a, &nsplit, &rows_per_split);
+    bool gram_rows = false;
+    int rc = prepare_steps(ws, a, ldg, sizeof(T) == sizeof(double), &nsplit, &rows_per_split,
+                           &gram_rows);
     if (rc) return rc;
     BlockTables *t = tables_of(ws);
     const int N = block_count(a.n, a.b);
@@ -2041,13 +2257,13 @@ static int block_sweeps(BlockWorkspace *ws, const BlockRunArgs &a, T *G, long ld
             const bool wait_v = split && step >= 2;
             if (a.b == 16)
                 e = launch_step<32, T>(ws, a, t, k, par, wait_v, pend_k, k == N - 1, nsplit,
-                                        rows_per_split, dctr + s, G, ldg, V, ldv, tol);
+                                        rows_per_split, gram_rows, dctr + s, G, ldg, V, ldv, tol);
             else if (a.b == 32)
                 e = launch_step<64, T>(ws, a, t, k, par, wait_v, pend_k, k == N - 1, nsplit,
-                                        rows_per_split, dctr + s, G, ldg, V, ldv, tol);
+                                        rows_per_split, gram_rows, dctr + s, G, ldg, V, ldv, tol);
             else
                 e = launch_step<128, T>(ws, a, t, k, par, wait_v, pend_k, k == N - 1, nsplit,
-                                        rows_per_split, dctr + s, G, ldg, V, ldv, tol);
+                                        rows_per_split, gram_rows, dctr + s, G, ldg, V, ldv, tol);
             pend_k = split ? k : -1;
         }
         if (split) {
