@@ -731,6 +731,13 @@ def main():
                                        "frac": round(solve_tf / FP64_MFMA_PEAK_TFS, 4),
                                        "basis": "sweeps x 2 n^2 (3 m + 2 n) flops / wall time "
                                                 "per solve"}
+        # what the GPU sustains on FP64 MFMAs alone (operands in registers, no
+        # memory access), for scale next to the published peak
+        att = {w: round(jevd.jevd_mfma_f64_rate(h, w, 4096), 2) for w in (1, 2, 4)}
+        roofline["fp64_mfma_register_only_tflops"] = {
+            "waves_per_simd_1": att[1], "waves_per_simd_2": att[2], "waves_per_simd_4": att[4],
+            "basis": "jevd_mfma_f64_rate: independent v_mfma_f64_16x16x4f64 from registers, "
+                     "every CU"}
 
     cpu = None
     gate = None

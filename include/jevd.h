@@ -330,6 +330,17 @@ int jevd_set_timing(jevd_handle_t h, int on);
 /* Diagnostics of the last jacobi_evd call on h. */
 int jevd_get_info(jevd_handle_t h, jevd_info *info);
 
+/* Measurement aid for the roofline of the block path (Sec. 2.2: the block
+ * update is a matrix product): the FP64 MFMA rate the GPU of h sustains on
+ * independent v_mfma_f64_16x16x4f64 instructions whose operands sit in
+ * registers (no memory access inside the loop), with waves_per_simd
+ * (1, 2 or 4) wavefronts per SIMD on every CU, each running iters x 8
+ * MFMAs.  *tflops receives 2048 x MFMAs / seconds / 1e12 from HIP events on
+ * the handle's stream.  Allocates and frees a small result buffer; blocks
+ * until done.  JEVD_EINVAL for a NULL h or tflops, waves_per_simd not in
+ * {1, 2, 4}, or iters < 1. */
+int jevd_mfma_f64_rate(jevd_handle_t h, int waves_per_simd, int iters, double *tflops);
+
 /* Static text for a status code. */
 const char *jevd_strerror(int status);
 

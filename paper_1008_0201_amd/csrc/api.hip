@@ -350,6 +350,57 @@ int jevd_get_info(jevd_handle_t h, jevd_info *info)
     return JEVD_OK;
 }
 
+namespace jevd {
+// Eight independent accumulators per wavefront, operands in registers; one
+// value per thread is written so that the MFMAs are not removed.
+__global__ __launch_bounds__(256) void k_mfma_rate(double *out, int iters, double a0)
+{
+    typedef double d4v __attribute__((ext_vector_type(4)));
+    d4v acc[8];
+    for (int q = 0; q < 8; ++q) acc[q] = d4v{0, 0, 0, 0};
+    const double a = a0 + threadIdx.x * 1e-9, b = 0.5 * a0;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+    }
+    double s = 0.0;
+    for (int q = 0; q < 8; ++q) s += acc[q][0] + acc[q][1] + acc[q][2] + acc[q][3];
+    out[blockIdx.x * 256 + threadIdx.x] = s;
+}
+}  // namespace jevd
+
+int jevd_mfma_f64_rate(jevd_handle_t h, int waves_per_simd, int iters, double *tflops)
+{
+    if (!h || !tflops || iters < 1 ||
+        (waves_per_simd != 1 && waves_per_simd != 2 && waves_per_simd != 4))
+        return JEVD_EINVAL;
+    int cus = 0;
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    const int grid = cus * waves_per_simd;   // four wavefronts (one per SIMD) per workgroup
+    double *buf = nullptr;
+    HIP_TRY(hipMalloc(&buf, sizeof(double) * (size_t)grid * 256));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = JEVD_OK;
+    float ms = 0.f;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = JEVD_EHIP;
+    for (int rep = 0; rep < 2 && rc == JEVD_OK; ++rep) {   // the first run warms up
+        if (hipEventRecord(e0, h->stream) != hipSuccess) rc = JEVD_EHIP;
+        jevd::k_mfma_rate<<<grid, 256, 0, h->stream>>>(buf, iters, 1.0);
+        if (rc == JEVD_OK && hipGetLastError() != hipSuccess) rc = JEVD_EHIP;
+        if (rc == JEVD_OK && hipEventRecord(e1, h->stream) != hipSuccess) rc = JEVD_EHIP;
+        if (rc == JEVD_OK && hipEventSynchronize(e1) != hipSuccess) rc = JEVD_EHIP;
+        if (rc == JEVD_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = JEVD_EHIP;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    if (rc != JEVD_OK) return rc;
+    const double mfmas = (double)grid * 4 * iters * 8;
+    *tflops = ms > 0.f ? 2048.0 * mfmas / (ms * 1e-3) / 1e12 : 0.0;
+    return JEVD_OK;
+}
+
 static int run_pointwise(jevd_handle_t h, int m, int n, double *G, int ldg, const signed char *dJ,
                          double tol, const jevd_opts &o, double *V, int ldv, int *sweeps_done)
 {

@@ -23,7 +23,7 @@ EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "je
            "jevd_batch_create", "jevd_batch_run", "jevd_batch_results", "jevd_batch_destroy",
            "jacobi_evd_batched", "jevd_canonicalize", "jevd_adjoint", "jevd_adjoint_noalloc",
            "jevd_autotune",
-           "jevd_tune_file", "jevd_tune_lookup", "jevd_tune_record")
+           "jevd_tune_file", "jevd_tune_lookup", "jevd_tune_record", "jevd_mfma_f64_rate")
 K_PAIR_STEP, K_GRAM, K_PIVOT_SOLVE, K_UPDATE = 0, 1, 2, 3
 
 
@@ -93,6 +93,7 @@ def lib():
         L.jevd_tune_file.argtypes = [ctypes.c_char_p]
         L.jevd_tune_lookup.argtypes = [_i, _i, _ip, _ip, _dp]
         L.jevd_tune_record.argtypes = [_i, _i, _i, _i, ctypes.c_double]
+        L.jevd_mfma_f64_rate.argtypes = [_vp, _i, _i, _dp]
         for name in EXPORTS:
             if name != "jevd_strerror":
                 getattr(L, name).restype = ctypes.c_int
@@ -187,6 +188,15 @@ def jevd_set_timing(h, on):
     st = lib().jevd_set_timing(h, 1 if on else 0)
     if st != JEVD_OK:
         raise JevdError(st, "jevd_set_timing")
+
+
+def jevd_mfma_f64_rate(h, waves_per_simd=4, iters=2048):
+    """TFLOP/s the GPU sustains on independent FP64 MFMAs from registers."""
+    t = ctypes.c_double(0.0)
+    st = lib().jevd_mfma_f64_rate(h, int(waves_per_simd), int(iters), ctypes.byref(t))
+    if st != JEVD_OK:
+        raise JevdError(st, "jevd_mfma_f64_rate")
+    return t.value
 
 
 def jevd_ordering(n, ordering):

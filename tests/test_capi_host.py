@@ -236,3 +236,15 @@ def test_auto_variant_untuned_shapes(tmp_path):
     assert B.jevd_validate(2050, 2050, 2050, None, 0.0, o, False, 2050, False, 2050) == B.JEVD_EINVAL
     o.pivot = B.PIVOT_NONE
     assert B.jevd_validate(2050, 2050, 2050, None, 0.0, o, False, 2050, False, 2050) == B.JEVD_OK
+
+
+def test_mfma_rate_rejects_bad_arguments():
+    """jevd_mfma_f64_rate checks its arguments before any device work."""
+    L = B.lib()
+    t = ctypes.c_double(-1.0)
+    assert L.jevd_mfma_f64_rate(None, 4, 16, ctypes.byref(t)) == B.JEVD_EINVAL
+    fake = ctypes.c_void_p(1)   # never dereferenced: the argument checks come first
+    for wps, iters in ((0, 16), (3, 16), (8, 16), (4, 0)):
+        assert L.jevd_mfma_f64_rate(fake, wps, iters, ctypes.byref(t)) == B.JEVD_EINVAL
+    assert L.jevd_mfma_f64_rate(fake, 4, 16, None) == B.JEVD_EINVAL
+    assert t.value == -1.0

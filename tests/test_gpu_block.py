@@ -184,3 +184,14 @@ def test_block_uneven_hyperbolic(solver, orc, n, m, b, full_block):
     wl = W.graded_hyperbolic(n, k=450 + n, grade=2.0, m=m)
     got = run(solver, wl.G, wl.J, wl.tol, 2 if full_block else 1, b)
     check(orc, wl.G, wl.J, wl.tol, b, full_block, got)
+
+
+def test_mfma_rate_diagnostic(solver):
+    """jevd_mfma_f64_rate (the register-only FP64 MFMA rate the bench reports
+    beside the roofline) returns a positive rate below the published peak
+    of 78.6 TFLOP/s, not lower with more wavefronts per SIMD by much."""
+    from paper_1008_0201_amd import jevd
+    r = {w: jevd.jevd_mfma_f64_rate(solver.h, w, 512) for w in (1, 2, 4)}
+    for w, t in r.items():
+        assert 1.0 < t < 78.6 * 1.05, (w, t)
+    assert r[4] >= 0.8 * r[1], r
