@@ -414,7 +414,8 @@ static int run_pointwise(jevd_handle_t h, int m, int n, double *G, int ldg, cons
         // whole solve in one workgroup (all sweeps inside the kernel)
         HIP_TRY(hipMemsetAsync(h->dctr, 0, sizeof(SweepCounters) * o.max_sweeps, h->stream));
         SmallSolveArgs a{G, m, n, (long)ldg, V, (long)ldv, dJ, tol, h->dpairs, h->dstep, nsteps,
-                         h->maxPairsPerStep, o.max_sweeps, h->dctr, h->dsweeps};
+                         h->maxPairsPerStep, o.max_sweeps, h->dctr, h->dsweeps,
+                         o.ordering == JEVD_ORD_ROWCYCLIC};
         HIP_TRY(h->timer.begin(h->stream, JEVD_K_PAIR_STEP));
         HIP_TRY(launch_small_solve(a, h->stream));
         HIP_TRY(h->timer.end(h->stream));

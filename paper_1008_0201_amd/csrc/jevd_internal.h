@@ -68,6 +68,7 @@ struct SmallSolveArgs {
     int max_sweeps;
     SweepCounters *ctr;  // max_sweeps slots
     int *sweeps_out;     // device
+    bool row_cyclic;     // the pairs are (p, q), p < q, in row order
 };
 
 // Optional kernel timing: a timed group of launches of one kernel class

@@ -528,6 +528,113 @@ __global__ __launch_bounds__(NW *kWave) void k_small_solve(
     if (threadIdx.x == 0) *sweeps_out = sweep;
 }
 
+// All sweeps of the row-cyclic ordering (the pairs (p, q), p < q, in row
+// order: strictly sequential) for m, n <= 64 in one wavefront, lane r holding
+// row r.  G and V sit in LDS column-major (pitch 64, rows past m or n zero).
+// The column p of the current row of pairs stays in registers for the whole
+// row; the next pair's column is read from LDS while the current pair is
+// transformed (it is not one of the pair's columns), so a pair's dependent
+// chain is its three dot products, their wavefront sums, the rotation
+// decision and transform, and the rotation.  The arithmetic is that of
+// small_pair (wave_sum, needs_rotation, transform_params, rotate_elems).
+constexpr int kRowCyclicMax = 64;
+
+// A DPP move of a double for patterns that have a source lane in every lane
+// (quad permutations, row mirrors): no old value is needed.
+template <int CTRL>
+__device__ __forceinline__ double dpp_all(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// wave_sum of three values with the stages interleaved (the same additions
+// in the same order as wave_sum, so the same totals).
+__device__ __forceinline__ void wave_sum3(double &x, double &y, double &z)
+{
+    x += dpp_all<0xB1>(x);
+    y += dpp_all<0xB1>(y);
+    z += dpp_all<0xB1>(z);
+    x += dpp_all<0x4E>(x);
+    y += dpp_all<0x4E>(y);
+    z += dpp_all<0x4E>(z);
+    x += dpp_all<0x141>(x);
+    y += dpp_all<0x141>(y);
+    z += dpp_all<0x141>(z);
+    x += dpp_all<0x140>(x);
+    y += dpp_all<0x140>(y);
+    z += dpp_all<0x140>(z);
+    const double x0 = read_lane(x, 0), x1 = read_lane(x, 16), x2 = read_lane(x, 32), x3 = read_lane(x, 48);
+    const double y0 = read_lane(y, 0), y1 = read_lane(y, 16), y2 = read_lane(y, 32), y3 = read_lane(y, 48);
+    const double z0 = read_lane(z, 0), z1 = read_lane(z, 16), z2 = read_lane(z, 32), z3 = read_lane(z, 48);
+    x = (x0 + x1) + (x2 + x3);
+    y = (y0 + y1) + (y2 + y3);
+    z = (z0 + z1) + (z2 + z3);
+}
+
+__global__ __launch_bounds__(kWave) void k_rowcyclic_solve(
+    double *__restrict__ G, int m, int n, long ldg, double *__restrict__ V, long ldv,
+    const signed char *__restrict__ J, double tol, int max_sweeps,
+    SweepCounters *__restrict__ ctr, int *__restrict__ sweeps_out)
+{
+    constexpr int P = kRowCyclicMax;
+    __shared__ double g[P * P], v[P * P];
+    __shared__ signed char js[P];
+    const int lane = threadIdx.x;
+    for (int c = 0; c < n; ++c) {
+        g[c * P + lane] = lane < m ? G[(size_t)c * ldg + lane] : 0.0;
+        v[c * P + lane] = (V && lane < n) ? V[(size_t)c * ldv + lane] : 0.0;
+    }
+    if (lane < n) js[lane] = J ? J[lane] : (signed char)1;
+    __syncthreads();
+    int sweep = 0;
+    while (sweep < max_sweeps) {
+        unsigned long long rot = 0, ncl = 0;
+        int nonfinite = 0;
+        for (int p = 0; p + 1 < n; ++p) {
+            double a = g[p * P + lane], va = v[p * P + lane];
+            double b = g[(p + 1) * P + lane], vb = v[(p + 1) * P + lane];
+            const signed char jp = js[p];
+            for (int q = p + 1; q < n; ++q) {
+                // the next pair's column (a repeat of column q on the last pair, unused)
+                const int qn = q + 1 < n ? q + 1 : q;
+                const double bn = g[qn * P + lane], vbn = v[qn * P + lane];
+                const bool same = jp == js[q];
+                double app = a * a, aqq = b * b, apq = a * b;
+                wave_sum3(app, aqq, apq);
+                if (!finite3(app, aqq, apq)) {
+                    nonfinite = 1;
+                } else if (needs_rotation(app, aqq, apq, tol)) {
+                    double c, s;
+                    ncl += transform_params(app, aqq, apq, same, c, s) ? 1 : 0;
+                    rotate_elems(a, b, c, s, same);
+                    rotate_elems(va, vb, c, s, same);
+                    g[q * P + lane] = b;
+                    v[q * P + lane] = vb;
+                    ++rot;
+                }
+                b = bn;
+                vb = vbn;
+            }
+            g[p * P + lane] = a;
+            v[p * P + lane] = va;
+        }
+        if (lane == 0) {
+            ctr[sweep].rotations = rot;
+            ctr[sweep].clamps = ncl;
+            ctr[sweep].nonfinite = nonfinite;
+        }
+        ++sweep;
+        if (rot == 0 || nonfinite) break;
+    }
+    for (int c = 0; c < n; ++c) {
+        if (lane < m) G[(size_t)c * ldg + lane] = g[c * P + lane];
+        if (V && lane < n) V[(size_t)c * ldv + lane] = v[c * P + lane];
+    }
+    if (lane == 0) *sweeps_out = sweep;
+}
+
 __global__ void k_identity(double *__restrict__ V, int n, long ldv)
 {
     const int c = blockIdx.x;
@@ -634,6 +741,11 @@ static hipError_t launch_small_nw(const SmallSolveArgs &a, hipStream_t st)
 
 hipError_t launch_small_solve(const SmallSolveArgs &a, hipStream_t st)
 {
+    if (a.row_cyclic && a.m <= kRowCyclicMax && a.n <= kRowCyclicMax) {
+        k_rowcyclic_solve<<<1, kWave, 0, st>>>(a.G, a.m, a.n, a.ldg, a.V, a.ldv, a.J, a.tol,
+                                               a.max_sweeps, a.ctr, a.sweeps_out);
+        return hipGetLastError();
+    }
     // one wavefront for strictly sequential orderings; otherwise up to 16
     if (a.max_pairs_per_step <= 1) return launch_small_nw<1>(a, st);
     if (a.max_pairs_per_step <= 4) return launch_small_nw<4>(a, st);

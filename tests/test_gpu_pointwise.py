@@ -82,6 +82,27 @@ def test_small_spd_rowcyclic_n64(solver, orc):
     print("n=64 row-cyclic sweeps gpu %d oracle %d" % (got["sweeps"], ref.sweeps))
 
 
+@pytest.mark.parametrize("m,n,ld,want_V", [(1, 1, None, True), (2, 2, None, True),
+                                            (5, 3, 9, True), (17, 17, None, False),
+                                            (40, 33, 41, True), (64, 50, None, True),
+                                            (64, 64, 70, True)])
+@pytest.mark.parametrize("indef", [False, True])
+def test_rowcyclic_one_wavefront(solver, orc, m, n, ld, want_V, indef):
+    """The row-cyclic ordering for m, n <= 64 (one wavefront, one row per
+    lane, the next pair's column read ahead): graded columns, odd and ragged
+    shapes, a padded leading dimension, with and without V, J = I and mixed
+    signs; eigenvalues, sweep count, U, V and G V against the oracle."""
+    g = np.random.default_rng(3000 + 100 * m + n + 7 * indef)
+    G = g.standard_normal((m, n)) * (10.0 ** g.uniform(-2, 2, size=n))[None, :]
+    J = None
+    if indef and n > 1:
+        J = np.ones(n, dtype=np.int8)
+        J[g.permutation(n)[: n // 2]] = -1
+    got = run_gpu(solver, G, J, n * EPS, W.ROWCYCLIC, want_V=want_V, ld=ld)
+    assert (got["V"] is None) == (not want_V)
+    check_against_oracle(orc, G, J, n * EPS, W.ROWCYCLIC, got)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 33, 64, 100, 128])
 @pytest.mark.parametrize("indef", [False, True])
 def test_small_modmod_single_workgroup(solver, orc, n, indef):
