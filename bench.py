@@ -200,10 +200,22 @@ def run_batched(args):
     opts = jevd.jevd_default_opts()
     opts.ordering = W.MODMODULUS
     opts.variant = jevd.VAR_POINTWISE
+    # untimed: the library measures its workgroup sizes per size class and
+    # the plan takes them from the tune table
+    t_tune = time.perf_counter()
+    if args.no_tune:
+        # the defaults: an empty table, not the one an earlier run left on
+        # the machine
+        import tempfile
+        jevd.jevd_tune_file(os.path.join(tempfile.mkdtemp(), "empty_tune.txt"))
+    else:
+        jevd.jevd_batch_autotune(h, want_v=True)
+    t_tune = time.perf_counter() - t_tune
     st, plan, keep = jevd.jevd_batch_create(h, ms, ns, gp, ms, Js, [w.tol for w in wls], opts,
                                             lp, up, ms, vp, ns)
     if st != 0:
         raise RuntimeError("jevd_batch_create: %s" % jevd.jevd_strerror(st))
+    plan_waves = jevd.jevd_batch_waves(plan)
 
     def step():
         Gd.copy_(G0)
@@ -259,8 +271,9 @@ def run_batched(args):
                 "kernel": "k_batch_solve",
                 "avg_launch_us": round(kern_ms * 1e3, 1), "bytes_per_launch": hbm,
                 "flops_per_launch": work, "fp64_vector_tflops": round(achieved, 3),
-                "timing": "HIP events around jevd_batch_run (queue reset + one persistent "
-                          "launch) on the solver stream",
+                "timing": "HIP events around jevd_batch_run on the solver stream (per launch "
+                          "group a queue reset + one persistent launch; groups after the "
+                          "first run at the same time on the plan's second stream)",
                 "bytes_basis": "instances with G in HBM: 16 m n bytes per parallel step (G read "
                                "and written) + V once per 32 steps; all: G, V loaded and stored "
                                "once"}
@@ -350,6 +363,8 @@ def run_batched(args):
                    "J": "I for even i, random +-1 for odd i", "ordering": "modified modulus",
                    "variant": "pointwise (batched)", "tol": "n_i eps",
                    "sweeps_range": [min(sw), max(sw)], "want_U": True, "want_V": True,
+                   "size_classes_n_max": [48, 96, 141, 256],
+                   "waves_per_class": plan_waves, "autotune_s": round(t_tune, 2),
                    "input_generation_s": round(t_gen, 1)},
         "single_call_loop_ms_per_batch": round(loop_s * 1e3, 1),
         "roofline": roofline,
@@ -537,7 +552,7 @@ def main():
     ap.add_argument("--block", type=int, default=None, help="override the autotuner's block width")
     ap.add_argument("--precision", type=int, default=None, help="override: 0 FP64, 1 mixed")
     ap.add_argument("--pivot", type=int, default=None, help="override: 0 none, 1 sign (Alg. 3.3)")
-    ap.add_argument("--no-tune", action="store_true", help="skip jevd_autotune (block 0: default)")
+    ap.add_argument("--no-tune", action="store_true", help="skip jevd_autotune / jevd_batch_autotune (defaults)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (profiling runs); no accuracy gate then")
     args = ap.parse_args()

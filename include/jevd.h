@@ -191,10 +191,20 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
  * tolerances (NULL or an entry <= 0: n_i * DBL_EPSILON).  opts->variant must
  * be JEVD_VAR_POINTWISE or JEVD_VAR_AUTO.  The plan refers to the caller's
  * buffers; they must stay valid while it is run.
+ * The instances are grouped by size into JEVD_BATCH_CLASSES classes
+ * (n <= 48, <= 96, <= 141, larger), each run with workgroups of 4, 8 or 16
+ * wavefronts (4, 2 or 1 instances at a time per CU, with that share of its
+ * LDS): the size jevd_batch_autotune measured fastest for the class on this
+ * machine when the class's per-step arrays fit that share, else 16.
+ * Consecutive classes of one size share a persistent launch (largest
+ * instances first); the largest class's launch runs on `stream`, the others
+ * at the same time on a second stream of the plan.
  * jevd_batch_run enqueues the solve of all instances on `stream` (a
  * hipStream_t; NULL: the handle's stream) and returns at once: it launches
- * two kernels and nothing else, so it may be captured in a HIP graph and
- * replayed.  Each run restarts from the current contents of the G_i.
+ * two kernels per launch group and, with more than one group, records two
+ * events (the second stream waits for `stream`'s prior work, and `stream`
+ * for the second stream's launches), so it may be captured in a HIP graph
+ * and replayed.  Each run restarts from the current contents of the G_i.
  * jevd_batch_results waits for the stream of the last run and copies out
  * the per-instance sweep counts and statuses (JEVD_OK, JEVD_ENOCONV,
  * JEVD_ENONFINITE); either array may be NULL.  It returns JEVD_OK if every
@@ -218,6 +228,33 @@ int jacobi_evd_batched(jevd_handle_t h, int batch, const int *m, const int *n,
                        const double *tol, const jevd_opts *opts, double *const *lambda,
                        double *const *U, const int *ldu, double *const *V, const int *ldv,
                        int *sweeps, int *status);
+
+#define JEVD_BATCH_CLASSES 4
+
+/* The workgroup size (wavefronts) each class of a plan runs with, 0 for an
+ * empty class: waves[JEVD_BATCH_CLASSES].  Host-only.  JEVD_EINVAL for NULL
+ * arguments. */
+int jevd_batch_waves(jevd_batch_t plan, int *waves);
+
+/* Measures, for each size class, a batch of seeded instances of a
+ * representative size (n = 40, 80, 128, 192; m = n; columns graded over two
+ * decades; J = I; V formed if want_v) with each workgroup size whose LDS
+ * share holds the class's step arrays (4, 8, 16 wavefronts), and records the
+ * fastest in the autotuner's table on the machine (the file of
+ * jevd_tune_file), where jevd_batch_create finds it.  waves_out (NULL or
+ * JEVD_BATCH_CLASSES entries) receives the choices.  Allocates and frees
+ * device memory (about 0.8 GB at most) and synchronises the handle's stream.
+ * JEVD_EINVAL for a NULL h or want_v not 0 or 1; JEVD_ENOMEM / JEVD_EHIP on
+ * device failures.  An unwritable table file is not an error. */
+int jevd_batch_autotune(jevd_handle_t h, int want_v, int *waves_out);
+
+/* The table's record for a size class (host-only): JEVD_EINVAL if none. */
+int jevd_batch_tune_lookup(int size_class, int *waves, double *ms);
+
+/* Records a size class's workgroup size (4, 8 or 16) and time in the table
+ * and rewrites its file; JEVD_EINVAL for a class outside
+ * [0, JEVD_BATCH_CLASSES), another size, or a negative time. */
+int jevd_batch_tune_record(int size_class, int waves, double ms);
 
 /*
  * Canonical outputs and the adjoint, for `batch` instances of one shape

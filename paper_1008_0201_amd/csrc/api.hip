@@ -36,10 +36,23 @@ struct jevd_batch_s {
     jevd_handle_t h = nullptr;
     int batch = 0;
     int ordering = 0, max_sweeps = 50, accumulate_v = 0;
-    int grid = 0;
+    // size classes (largest first in d_order): offset, count, workgroup size
+    // in wavefronts and grid of each class's launch
+    int cls_off[kBatchClasses] = {}, cls_cnt[kBatchClasses] = {};
+    int cls_waves[kBatchClasses] = {};
+    // launches: consecutive classes of one workgroup size share a launch and
+    // its queue (so longest-first holds across them); the first launch runs
+    // on the caller's stream, the others at the same time on a second
+    // stream, so that their workgroups take the CUs the first launch frees
+    // in its tail
+    int ngrp = 0;
+    int grp_off[kBatchClasses] = {}, grp_cnt[kBatchClasses] = {};
+    int grp_waves[kBatchClasses] = {}, grp_grid[kBatchClasses] = {};
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     BatchInst *d_inst = nullptr;
     int *d_order = nullptr;
-    int *d_queue = nullptr;
+    int *d_queue = nullptr;    // one counter per launch
     int *d_sweeps = nullptr;   // per instance
     int *d_status = nullptr;   // per instance
     signed char *d_J = nullptr;
@@ -749,6 +762,9 @@ int jevd_batch_destroy(jevd_batch_t p)
     if (p->d_sweeps) (void)hipFree(p->d_sweeps);
     if (p->d_status) (void)hipFree(p->d_status);
     if (p->d_J) (void)hipFree(p->d_J);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->aux) (void)hipStreamDestroy(p->aux);
     delete p;
     return JEVD_OK;
 }
@@ -791,7 +807,6 @@ int jevd_batch_create(jevd_handle_t h, int batch, const int *m, const int *n, do
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
         cus = 256;
-    p->grid = std::min(batch, cus);   // one persistent workgroup per CU (it takes all of LDS)
     std::vector<signed char> hJ(jtotal > 0 ? jtotal : 1);
     std::vector<size_t> joff(batch, (size_t)-1);
     size_t off = 0;
@@ -809,7 +824,7 @@ int jevd_batch_create(jevd_handle_t h, int batch, const int *m, const int *n, do
     hipError_t e;
     if ((e = hipMalloc((void **)&p->d_inst, sizeof(BatchInst) * batch)) != hipSuccess) return fail(e);
     if ((e = hipMalloc((void **)&p->d_order, sizeof(int) * batch)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc((void **)&p->d_queue, sizeof(int))) != hipSuccess) return fail(e);
+    if ((e = hipMalloc((void **)&p->d_queue, sizeof(int) * kBatchClasses)) != hipSuccess) return fail(e);
     if ((e = hipMalloc((void **)&p->d_sweeps, sizeof(int) * batch)) != hipSuccess) return fail(e);
     if ((e = hipMalloc((void **)&p->d_status, sizeof(int) * batch)) != hipSuccess) return fail(e);
     if ((e = hipMalloc((void **)&p->d_J, hJ.size())) != hipSuccess) return fail(e);
@@ -827,12 +842,48 @@ int jevd_batch_create(jevd_handle_t h, int batch, const int *m, const int *n, do
         d.ldv = d.V ? ldv[i] : n[i];
         d.ldu = d.U ? ldu[i] : m[i];
     }
-    // longest processing time first: about n^2 m work per sweep
+    // by size class, largest class first, and within a class longest
+    // processing time first (about n^2 m work per sweep); each class is one
+    // launch with its own workgroup size: the tuned one if the class's step
+    // arrays fit its LDS share, else 16 wavefronts
     std::vector<int> order(batch);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const int ca = batch_class_of(n[a]), cb = batch_class_of(n[b]);
+        if (ca != cb) return ca > cb;
         return (double)n[a] * n[a] * m[a] > (double)n[b] * n[b] * m[b];
     });
+    int nmax[kBatchClasses] = {};
+    for (int i = 0; i < batch; ++i) {
+        const int c = batch_class_of(n[i]);
+        ++p->cls_cnt[c];
+        nmax[c] = std::max(nmax[c], n[i]);
+    }
+    for (int c = kBatchClasses - 1, off = 0; c >= 0; --c) {
+        p->cls_off[c] = off;
+        off += p->cls_cnt[c];
+        if (p->cls_cnt[c] == 0) continue;
+        const int tw = tuned_batch_waves(c);
+        const int w = (tw > 0 && batch_waves_fit(tw, nmax[c])) ? tw : default_batch_waves(c);
+        p->cls_waves[c] = batch_waves_fit(w, nmax[c]) ? w : 16;
+        if (p->ngrp > 0 && p->grp_waves[p->ngrp - 1] == p->cls_waves[c]) {
+            p->grp_cnt[p->ngrp - 1] += p->cls_cnt[c];
+        } else {
+            p->grp_off[p->ngrp] = p->cls_off[c];
+            p->grp_cnt[p->ngrp] = p->cls_cnt[c];
+            p->grp_waves[p->ngrp] = p->cls_waves[c];
+            ++p->ngrp;
+        }
+    }
+    for (int g = 0; g < p->ngrp; ++g)
+        p->grp_grid[g] = std::min(p->grp_cnt[g], cus * (16 / p->grp_waves[g]));
+    if (p->ngrp > 1) {
+        if ((e = hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+        if ((e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming)) != hipSuccess)
+            return fail(e);
+        if ((e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming)) != hipSuccess)
+            return fail(e);
+    }
     if ((e = hipMemcpy(p->d_inst, hi.data(), sizeof(BatchInst) * batch, hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e);
     if ((e = hipMemcpy(p->d_order, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice)) != hipSuccess)
@@ -846,8 +897,22 @@ int jevd_batch_run(jevd_batch_t p, void *stream)
 {
     if (!p) return JEVD_EINVAL;
     hipStream_t st = stream ? (hipStream_t)stream : p->h->stream;
-    HIP_TRY(launch_batch(p->d_inst, p->d_order, p->batch, p->d_queue, p->ordering, p->max_sweeps,
-                         p->accumulate_v, p->d_sweeps, p->d_status, p->grid, st));
+    // the second stream starts from the caller's stream's prior work (event
+    // recorded before the first launch) and the caller's stream waits for it
+    // at the end; both are events, so a graph capture of the caller's stream
+    // takes in the second stream's launches
+    if (p->ngrp > 1) {
+        HIP_TRY(hipEventRecord(p->ev_fork, st));
+        HIP_TRY(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
+    }
+    for (int g = 0; g < p->ngrp; ++g)
+        HIP_TRY(launch_batch(p->d_inst, p->d_order + p->grp_off[g], p->grp_cnt[g], p->d_queue + g,
+                             p->ordering, p->max_sweeps, p->accumulate_v, p->d_sweeps, p->d_status,
+                             p->grp_grid[g], p->grp_waves[g], g == 0 ? st : p->aux));
+    if (p->ngrp > 1) {
+        HIP_TRY(hipEventRecord(p->ev_join, p->aux));
+        HIP_TRY(hipStreamWaitEvent(st, p->ev_join, 0));
+    }
     p->last = st;
     p->ran = true;
     return JEVD_OK;
@@ -879,6 +944,102 @@ int jacobi_evd_batched(jevd_handle_t h, int batch, const int *m, const int *n, d
     if (st == JEVD_OK) st = jevd_batch_results(p, sweeps, status);
     jevd_batch_destroy(p);
     return st;
+}
+
+int jevd_batch_waves(jevd_batch_t p, int *waves)
+{
+    if (!p || !waves) return JEVD_EINVAL;
+    for (int c = 0; c < kBatchClasses; ++c) waves[c] = p->cls_cnt[c] > 0 ? p->cls_waves[c] : 0;
+    return JEVD_OK;
+}
+
+int jevd_batch_autotune(jevd_handle_t h, int want_v, int *waves_out)
+{
+    if (!h || (want_v != 0 && want_v != 1)) return JEVD_EINVAL;
+    // a representative size per class and the count of instances timed
+    static const int rep_n[kBatchClasses] = {40, 80, 128, 192};
+    static const int count[kBatchClasses] = {2048, 1024, 1024, 512};
+    HIP_TRY(hipSetDevice(h->device));
+    HIP_TRY(prepare_batch_kernel());
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    for (int c = 0; c < kBatchClasses; ++c) {
+        const int n = rep_n[c], K = count[c];
+        const size_t nn = (size_t)n * n;
+        double *G0 = nullptr, *G = nullptr, *V = nullptr, *lam = nullptr;
+        BatchInst *d_inst = nullptr;
+        int *d_order = nullptr, *d_queue = nullptr, *d_sweeps = nullptr, *d_status = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        int rc = JEVD_OK, best = -1;
+        double best_ms = 0.0;
+        auto ok = [&](hipError_t e) {
+            if (e != hipSuccess && rc == JEVD_OK) rc = e == hipErrorOutOfMemory ? JEVD_ENOMEM : JEVD_EHIP;
+            return rc == JEVD_OK;
+        };
+        if (ok(hipMalloc(&G0, sizeof(double) * nn * K)) && ok(hipMalloc(&G, sizeof(double) * nn * K)) &&
+            (!want_v || ok(hipMalloc(&V, sizeof(double) * nn * K))) &&
+            ok(hipMalloc(&lam, sizeof(double) * (size_t)n * K)) &&
+            ok(hipMalloc(&d_inst, sizeof(BatchInst) * K)) && ok(hipMalloc(&d_order, sizeof(int) * K)) &&
+            ok(hipMalloc(&d_queue, sizeof(int))) && ok(hipMalloc(&d_sweeps, sizeof(int) * K)) &&
+            ok(hipMalloc(&d_status, sizeof(int) * K)) && ok(hipEventCreate(&e0)) &&
+            ok(hipEventCreate(&e1))) {
+            std::vector<BatchInst> hi(K);
+            std::vector<int> order(K);
+            for (int i = 0; i < K; ++i) {
+                BatchInst &d = hi[i];
+                d.G = G + nn * i;
+                d.V = want_v ? V + nn * i : nullptr;
+                d.lambda = lam + (size_t)n * i;
+                d.U = nullptr;
+                d.J = nullptr;
+                d.tol = n * DBL_EPSILON;
+                d.m = d.n = d.ldg = d.ldv = d.ldu = n;
+                order[i] = i;
+            }
+            if (ok(hipMemcpy(d_inst, hi.data(), sizeof(BatchInst) * K, hipMemcpyHostToDevice)) &&
+                ok(hipMemcpy(d_order, order.data(), sizeof(int) * K, hipMemcpyHostToDevice)) &&
+                ok(launch_fill_batch(G0, n, n, K, 1000 + c, h->stream))) {
+                for (int w : {4, 8, 16}) {
+                    if (!batch_waves_fit(w, n)) continue;
+                    const int grid = std::min(K, cus * (16 / w));
+                    float best_w = 0.f;
+                    for (int rep = 0; rep < 2 && rc == JEVD_OK; ++rep) {
+                        float ms = 0.f;
+                        if (ok(hipMemcpyAsync(G, G0, sizeof(double) * nn * K, hipMemcpyDeviceToDevice,
+                                              h->stream)) &&
+                            ok(hipEventRecord(e0, h->stream)) &&
+                            ok(launch_batch(d_inst, d_order, K, d_queue, JEVD_ORD_MODMODULUS, 50, 0, d_sweeps,
+                                            d_status, grid, w, h->stream)) &&
+                            ok(hipEventRecord(e1, h->stream)) && ok(hipEventSynchronize(e1)) &&
+                            ok(hipEventElapsedTime(&ms, e0, e1)))
+                            best_w = (rep == 0) ? ms : std::min(best_w, ms);
+                    }
+                    if (rc != JEVD_OK) break;
+                    if (best < 0 || best_w < best_ms) {
+                        best = w;
+                        best_ms = best_w;
+                    }
+                }
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(G0);
+        (void)hipFree(G);
+        (void)hipFree(V);
+        (void)hipFree(lam);
+        (void)hipFree(d_inst);
+        (void)hipFree(d_order);
+        (void)hipFree(d_queue);
+        (void)hipFree(d_sweeps);
+        (void)hipFree(d_status);
+        if (rc != JEVD_OK) return rc;
+        (void)jevd_batch_tune_record(c, best, best_ms);   // an unwritable table file is not an error
+        if (waves_out) waves_out[c] = best;
+    }
+    return JEVD_OK;
 }
 
 }  // extern "C"

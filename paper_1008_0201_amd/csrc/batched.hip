@@ -31,8 +31,15 @@ struct BatchInst {
     int m, n, ldg, ldv, ldu;
 };
 
-constexpr int kBatchWaves = 16;
+// A workgroup of NW wavefronts (4, 8 or 16) and NW / 16 of the LDS, so that
+// 16 / NW workgroups (instances) share a CU; the wavefronts of a CU are 16
+// in every configuration.
+constexpr int kBatchWaves = 16;   // the most wavefronts per workgroup
 constexpr size_t kBatchLdsBytes = 160 * 1024 - 256;   // the rest: static arrays
+__host__ __device__ constexpr size_t batch_lds_bytes(int nw)
+{
+    return (kBatchLdsBytes * (size_t)nw / kBatchWaves) & ~(size_t)15;
+}
 
 // pairs of step st of the ordering over n columns (row-cyclic: one pair;
 // modulus family: closed form)
@@ -56,7 +63,7 @@ struct InstCtx {
     int vsteps;            // 0: V is rotated at once
     double *vlog;          // LDS: vsteps x (n/2 + 1) x (c, s)
     int *vflag;            // LDS: vsteps x (n/2 + 1) transform types
-    double *vrows;         // LDS: kBatchWaves * kVRows rows of V, n each
+    double *vrows;         // LDS: NW * kVRows rows of V, n each
 };
 
 constexpr int kVRows = 2;   // rows of V per wavefront in the deferred apply
@@ -94,11 +101,12 @@ __device__ __forceinline__ double group_sum(double x, int C)
 //      wavefront;
 //   3. rotation of the G (and V) column pairs by the same lane groups.
 // g and v are LDS or global pointers of one kind each (see the callers).
+template <int NW>
 __device__ __forceinline__ void modulus_step(double *g, long ldg, double *v, long ldv,
                                              const InstCtx &c, int k, bool modified,
                                              unsigned &rot, int &bad)
 {
-    constexpr int NW = kBatchWaves, BS = NW * 64;
+    constexpr int BS = NW * 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = c.n, m = c.m;
     const int np = modulus_step_pairs(n, k, modified);
@@ -278,12 +286,11 @@ __device__ __forceinline__ void two_pairs(double *g, long ldg, double *v, long l
 
 // One step over G in global memory by the register path (R > 0; two pairs
 // per wavefront for R <= 2, one for R = 4, registers permitting).
-template <int R>
+template <int NW, int R>
 __device__ __forceinline__ void global_step(double *g, long ldg, double *v, long ldv,
                                             const InstCtx &c, int k, bool modified, unsigned &rot,
                                             int &bad, double *logcs, int *logfl)
 {
-    constexpr int NW = kBatchWaves;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int np = modulus_step_pairs(c.n, k, modified);
     if constexpr (R <= 2) {
@@ -306,14 +313,15 @@ __device__ __forceinline__ void global_step(double *g, long ldg, double *v, long
 }
 
 // Applies the logged transforms of steps kfirst .. kfirst + nsteps - 1 to V
-// (HBM, column-major): blocks of kBatchWaves * kVRows rows are staged in LDS;
+// (HBM, column-major): blocks of NW * kVRows rows are staged in LDS;
 // a wavefront owns kVRows rows and runs every logged step on them, lanes over
 // the step's pairs.  A row's elements are rotated in the same order as by
 // immediate application, so V is the same to the bit.
+template <int NW>
 __device__ __forceinline__ void apply_v_log(double *v, long ldv, const InstCtx &c, int kfirst,
                                             int nsteps, bool modified)
 {
-    constexpr int NW = kBatchWaves, BS = NW * 64, RB = NW * kVRows;
+    constexpr int BS = NW * 64, RB = NW * kVRows;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = c.n, lp = n / 2 + 1;
     for (int r0 = 0; r0 < n; r0 += RB) {
@@ -401,12 +409,11 @@ __device__ __forceinline__ void one_pair_loop(double *g, long ldg, double *v, lo
 
 // All sweeps of one instance on (g, v); returns the status and sets sweeps.
 // R = 0: the phased step (G in LDS, or m > 256); R > 0: the register step.
-template <int R>
+template <int NW, int R>
 __device__ __forceinline__ int sweep_instance(double *g, long ldg, double *v, long ldv,
                                               const InstCtx &c, int ordering, int max_sweeps,
                                               int &sweeps, unsigned *s_rot, int *s_bad)
 {
-    constexpr int NW = kBatchWaves;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = c.n;
     int sweep = 0, status = JEVD_ENOCONV;
@@ -425,17 +432,17 @@ __device__ __forceinline__ int sweep_instance(double *g, long ldg, double *v, lo
                 const int lp = n / 2 + 1;
                 int inchunk = 0, kfirst = 1;
                 for (int k = 1; k <= n; ++k) {
-                    global_step<R>(g, ldg, defer ? nullptr : v, ldv, c, k, modified, rot, bad,
+                    global_step<NW, R>(g, ldg, defer ? nullptr : v, ldv, c, k, modified, rot, bad,
                                    defer ? c.vlog + 2 * (size_t)inchunk * lp : nullptr,
                                    defer ? c.vflag + (size_t)inchunk * lp : nullptr);
                     if (defer && (++inchunk == c.vsteps || k == n)) {
-                        apply_v_log(v, ldv, c, kfirst, inchunk, modified);
+                        apply_v_log<NW>(v, ldv, c, kfirst, inchunk, modified);
                         inchunk = 0;
                         kfirst = k + 1;
                     }
                 }
             } else {
-                for (int k = 1; k <= n; ++k) modulus_step(g, ldg, v, ldv, c, k, modified, rot, bad);
+                for (int k = 1; k <= n; ++k) modulus_step<NW>(g, ldg, v, ldv, c, k, modified, rot, bad);
             }
         }
         // workgroup totals: rotations and the non-finite flag
@@ -471,16 +478,20 @@ __device__ __forceinline__ int sweep_instance(double *g, long ldg, double *v, lo
     return status;
 }
 
-__global__ __launch_bounds__(kBatchWaves * 64) void k_batch_solve(
+// Sixteen wavefronts per CU in every configuration (16 / NW workgroups), so
+// the register budget is that of four wavefronts per SIMD.
+template <int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_solve(
     const BatchInst *__restrict__ inst, const int *__restrict__ order, int batch,
     int *__restrict__ queue, int ordering, int max_sweeps, int accumulate_v,
     int *__restrict__ sweeps_out, int *__restrict__ status_out)
 {
-    constexpr int BS = kBatchWaves * 64;
+    constexpr int BS = NW * 64;
+    constexpr size_t LB = batch_lds_bytes(NW);   // this workgroup's LDS
     extern __shared__ double lds[];
     __shared__ int s_idx;
-    __shared__ unsigned s_rot[kBatchWaves];
-    __shared__ int s_bad[kBatchWaves];
+    __shared__ unsigned s_rot[NW];
+    __shared__ int s_bad[NW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     for (;;) {
@@ -496,12 +507,22 @@ __global__ __launch_bounds__(kBatchWaves * 64) void k_batch_solve(
         // when they fit beside the signs and step arrays at the top of LDS,
         // else in place in global memory
         const size_t aux = batch_aux_bytes(n);
+        if (aux > LB) {
+            // the step arrays do not fit this workgroup's LDS (the host
+            // assigns such sizes to 16-wavefront workgroups only)
+            if (tid == 0) {
+                sweeps_out[which] = 0;
+                status_out[which] = JEVD_EINVAL;
+            }
+            __syncthreads();
+            continue;
+        }
         const size_t gbytes = (size_t)m * n * sizeof(double);
         const size_t vbytes = d.V ? (size_t)n * n * sizeof(double) : 0;
-        const bool lg = gbytes + aux <= kBatchLdsBytes;
-        const bool lv = d.V && gbytes + vbytes + aux <= kBatchLdsBytes;
+        const bool lg = gbytes + aux <= LB;
+        const bool lv = d.V && gbytes + vbytes + aux <= LB;
         const size_t pairs = (size_t)n / 2 + 1;
-        char *top = (char *)lds + (kBatchLdsBytes - aux);
+        char *top = (char *)lds + (LB - aux);
         InstCtx c;
         c.m = m;
         c.n = n;
@@ -518,14 +539,14 @@ __global__ __launch_bounds__(kBatchWaves * 64) void k_batch_solve(
         if (!lg && d.V && m <= 256) {
             // G in HBM (the register path): LDS below the step arrays holds
             // the V row blocks and the transform log of vsteps steps
-            const size_t free_bytes = kBatchLdsBytes - aux;
-            const size_t rows_bytes = (size_t)kBatchWaves * kVRows * n * sizeof(double);
+            const size_t free_bytes = LB - aux;
+            const size_t rows_bytes = (size_t)NW * kVRows * n * sizeof(double);
             const size_t per_step = pairs * (2 * sizeof(double) + sizeof(int));
             if (free_bytes > rows_bytes + 4 * per_step) {
                 size_t vs = (free_bytes - rows_bytes) / per_step;
                 c.vsteps = (int)(vs > 32 ? 32 : vs);
                 c.vrows = lds;
-                c.vlog = lds + (size_t)kBatchWaves * kVRows * n;
+                c.vlog = lds + (size_t)NW * kVRows * n;
                 c.vflag = (int *)(c.vlog + 2 * (size_t)c.vsteps * pairs);
             }
         }
@@ -544,19 +565,19 @@ __global__ __launch_bounds__(kBatchWaves * 64) void k_batch_solve(
         __syncthreads();
         int sweep = 0, status;
         if (lg && lv)
-            status = sweep_instance<0>(lds, m, lds + (size_t)m * n, n, c, ordering, max_sweeps, sweep,
+            status = sweep_instance<NW, 0>(lds, m, lds + (size_t)m * n, n, c, ordering, max_sweeps, sweep,
                                        s_rot, s_bad);
         else if (lg)
-            status = sweep_instance<0>(lds, m, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
+            status = sweep_instance<NW, 0>(lds, m, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
                                        s_bad);
         else if (m <= 128)
-            status = sweep_instance<2>(d.G, d.ldg, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
+            status = sweep_instance<NW, 2>(d.G, d.ldg, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
                                        s_bad);
         else if (m <= 256)
-            status = sweep_instance<4>(d.G, d.ldg, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
+            status = sweep_instance<NW, 4>(d.G, d.ldg, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
                                        s_bad);
         else
-            status = sweep_instance<0>(d.G, d.ldg, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
+            status = sweep_instance<NW, 0>(d.G, d.ldg, d.V, d.ldv, c, ordering, max_sweeps, sweep, s_rot,
                                        s_bad);
         // the final iterate back to G (and V), then lambda_i = j_i ||g_i||^2 and
         // u_i = g_i / ||g_i|| (U may be G itself)
@@ -568,7 +589,7 @@ __global__ __launch_bounds__(kBatchWaves * 64) void k_batch_solve(
                 d.V[(size_t)cc * d.ldv + r] = lds[(size_t)m * n + (size_t)cc * n + r];
             }
         __syncthreads();
-        for (int cc = wave; cc < n; cc += kBatchWaves) {
+        for (int cc = wave; cc < n; cc += NW) {
             const double *gc = lg ? lds + (size_t)cc * m : d.G + (size_t)cc * d.ldg;
             double s2 = 0.0;
             for (int r = lane; r < m; r += 64) s2 = fma(gc[r], gc[r], s2);
@@ -592,20 +613,89 @@ __global__ void k_reset_queue(int *queue) { *queue = 0; }
 
 hipError_t prepare_batch_kernel()
 {
-    return hipFuncSetAttribute((const void *)k_batch_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kBatchLdsBytes);
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void *)k_batch_solve<4>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)batch_lds_bytes(4))) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)k_batch_solve<8>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)batch_lds_bytes(8))) != hipSuccess)
+        return e;
+    return hipFuncSetAttribute((const void *)k_batch_solve<16>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)batch_lds_bytes(16));
+}
+
+bool batch_waves_supported(int waves) { return waves == 4 || waves == 8 || waves == 16; }
+
+int batch_class_of(int n)
+{
+    for (int c = 0; c < kBatchClasses; ++c)
+        if (n <= kBatchClassMax[c]) return c;
+    return kBatchClasses - 1;
+}
+
+int default_batch_waves(int cls)
+{
+    (void)cls;
+    return kBatchWaves;
+}
+
+bool batch_waves_fit(int waves, int nmax)
+{
+    return batch_waves_supported(waves) && batch_aux_bytes(nmax) <= batch_lds_bytes(waves);
+}
+
+// Seeded fill for the tuner's instances: x_i = (2 u_i - 1) 10^(2 w_c - 1)
+// with u_i, w_c uniform from a counter hash (splitmix64) of (seed, i) and
+// (seed, column c), so the columns are graded over two decades.
+__device__ __forceinline__ double hash_unit(unsigned long long x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return (double)(x >> 11) * 0x1.0p-53;
+}
+
+__global__ void k_fill_batch(double *G, int m, int n, long count, unsigned long long seed)
+{
+    const long total = count * (long)m * n;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total;
+         i += (long)gridDim.x * blockDim.x) {
+        const long col = i / m;   // column over all instances
+        const double w = hash_unit(seed * 0x100000001B3ull + 2 * col + 1);
+        G[i] = (2.0 * hash_unit(seed ^ (0xA5A5A5A5ull + 2 * i)) - 1.0) * exp10(2.0 * w - 1.0);
+    }
+}
+
+hipError_t launch_fill_batch(double *G, int m, int n, long count, unsigned long long seed,
+                             hipStream_t st)
+{
+    k_fill_batch<<<1024, 256, 0, st>>>(G, m, n, count, seed);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchInst *inst, const int *order, int batch, int *queue,
                         int ordering, int max_sweeps, int accumulate_v, int *sweeps, int *status,
-                        int grid, hipStream_t st)
+                        int grid, int waves, hipStream_t st)
 {
     // the queue is reset by a kernel (not a memset), so the pair of launches
     // can be captured in a graph and replayed
     k_reset_queue<<<1, 1, 0, st>>>(queue);
-    k_batch_solve<<<grid, kBatchWaves * 64, kBatchLdsBytes, st>>>(inst, order, batch, queue, ordering,
-                                                                  max_sweeps, accumulate_v, sweeps,
-                                                                  status);
+    if (waves == 4)
+        k_batch_solve<4><<<grid, 4 * 64, batch_lds_bytes(4), st>>>(inst, order, batch, queue, ordering,
+                                                                   max_sweeps, accumulate_v, sweeps,
+                                                                   status);
+    else if (waves == 8)
+        k_batch_solve<8><<<grid, 8 * 64, batch_lds_bytes(8), st>>>(inst, order, batch, queue, ordering,
+                                                                   max_sweeps, accumulate_v, sweeps,
+                                                                   status);
+    else
+        k_batch_solve<16><<<grid, 16 * 64, batch_lds_bytes(16), st>>>(inst, order, batch, queue,
+                                                                      ordering, max_sweeps,
+                                                                      accumulate_v, sweeps, status);
     return hipGetLastError();
 }
 

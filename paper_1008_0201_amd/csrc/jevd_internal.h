@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/jevd.h"
+
 #include "device_math.h"
 
 namespace jevd {
@@ -176,7 +178,19 @@ constexpr int kBatchMaxN = 4096;   // largest n_i of a batched solve
 hipError_t prepare_batch_kernel();  // once before the first launch (sets the LDS limit)
 hipError_t launch_batch(const BatchInst *inst, const int *order, int batch, int *queue,
                         int ordering, int max_sweeps, int accumulate_v, int *sweeps, int *status,
-                        int grid, hipStream_t st);
+                        int grid, int waves, hipStream_t st);
+bool batch_waves_supported(int waves);
+// Size classes of a batched solve: instances with kBatchClassMax[c - 1] < n
+// <= kBatchClassMax[c] form class c, each launched with its own workgroup
+// size (wavefronts: 4, 8 or 16, the tuned or the default one).
+constexpr int kBatchClasses = JEVD_BATCH_CLASSES;
+constexpr int kBatchClassMax[kBatchClasses] = {48, 96, 141, kBatchMaxN};
+int batch_class_of(int n);
+int default_batch_waves(int cls);
+int tuned_batch_waves(int cls);           // -1: not measured
+bool batch_waves_fit(int waves, int nmax);  // the step arrays of n <= nmax fit the LDS share
+hipError_t launch_fill_batch(double *G, int m, int n, long count, unsigned long long seed,
+                             hipStream_t st);
 hipError_t launch_small_solve(const SmallSolveArgs &a, hipStream_t st);
 hipError_t launch_sum_slots(unsigned *slot_rot, unsigned *slot_clamp, int nslots,
                             SweepCounters *ctr, hipStream_t st);

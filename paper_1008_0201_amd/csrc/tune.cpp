@@ -7,6 +7,9 @@
 //
 // The table is kept per process and mirrored to a text file, one line per
 // shape: "m n block variant ms" (the last record of a shape wins).  The
+// batched solve's records, one per size class, are lines "batch class
+// waves ms": the workgroup size (wavefronts) measured fastest for the class
+// by jevd_batch_autotune, which jevd_batch_create then uses.  The
 // file is JEVD_TUNE_FILE if set, else $HOME/.cache/jevd_tune.txt, else
 // nothing is persisted; jevd_tune_file() points it elsewhere.  Host code
 // only: no device work.
@@ -21,6 +24,7 @@
 
 #include "../../include/jevd.h"
 #include "block.h"
+#include "jevd_internal.h"
 
 namespace jevd {
 namespace {
@@ -30,8 +34,15 @@ struct TuneEntry {
     double ms;
 };
 
+// batched solve: the workgroup size measured fastest for a size class
+struct BatchTuneEntry {
+    int cls, waves;
+    double ms;
+};
+
 std::mutex g_mu;
 std::vector<TuneEntry> g_tab;
+std::vector<BatchTuneEntry> g_btab;
 std::string g_path;
 bool g_loaded = false;
 
@@ -50,6 +61,21 @@ bool valid_entry(const TuneEntry &e)
     if (e.variant == JEVD_VAR_POINTWISE) return e.block == 0;
     return (e.variant == JEVD_VAR_BLOCK_ORIENTED || e.variant == JEVD_VAR_FULL_BLOCK) &&
            block_shape_supported(e.m, e.n, e.block);
+}
+
+bool valid_batch_entry(const BatchTuneEntry &e)
+{
+    return e.cls >= 0 && e.cls < kBatchClasses && batch_waves_supported(e.waves) && e.ms >= 0.0;
+}
+
+void put_batch(const BatchTuneEntry &e)
+{
+    for (BatchTuneEntry &x : g_btab)
+        if (x.cls == e.cls) {
+            x = e;
+            return;
+        }
+    g_btab.push_back(e);
 }
 
 void put(const TuneEntry &e)
@@ -71,11 +97,17 @@ void load_locked()
     FILE *f = std::fopen(g_path.c_str(), "r");
     if (!f) return;
     TuneEntry e;
+    BatchTuneEntry be;
     char line[256];
-    while (std::fgets(line, sizeof line, f))
-        if (std::sscanf(line, "%d %d %d %d %lf", &e.m, &e.n, &e.block, &e.variant, &e.ms) == 5 &&
-            valid_entry(e))
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "batch %d %d %lf", &be.cls, &be.waves, &be.ms) == 3) {
+            if (valid_batch_entry(be)) put_batch(be);
+        } else if (std::sscanf(line, "%d %d %d %d %lf", &e.m, &e.n, &e.block, &e.variant, &e.ms) ==
+                       5 &&
+                   valid_entry(e)) {
             put(e);
+        }
+    }
     std::fclose(f);
 }
 
@@ -103,6 +135,7 @@ int save_locked()
     if (!f) return JEVD_EINVAL;
     for (const TuneEntry &e : g_tab)
         std::fprintf(f, "%d %d %d %d %.6f\n", e.m, e.n, e.block, e.variant, e.ms);
+    for (const BatchTuneEntry &e : g_btab) std::fprintf(f, "batch %d %d %.6f\n", e.cls, e.waves, e.ms);
     std::fclose(f);
     if (std::rename(tmp.c_str(), g_path.c_str()) != 0) return JEVD_EINVAL;
     return JEVD_OK;
@@ -128,6 +161,15 @@ int tuned_block_width(int m, int n)
     return (lookup_locked(m, n, &e) && e.block > 0) ? e.block : -1;
 }
 
+int tuned_batch_waves(int cls)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_loaded_locked();
+    for (const BatchTuneEntry &e : g_btab)
+        if (e.cls == cls) return e.waves;
+    return -1;
+}
+
 int tuned_variant(int m, int n)
 {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -145,6 +187,7 @@ int jevd_tune_file(const char *path)
 {
     std::lock_guard<std::mutex> lk(g_mu);
     g_tab.clear();
+    g_btab.clear();
     g_path = path ? std::string(path) : default_path();
     load_locked();
     return JEVD_OK;
@@ -168,6 +211,29 @@ int jevd_tune_record(int m, int n, int block, int variant, double ms)
     std::lock_guard<std::mutex> lk(g_mu);
     ensure_loaded_locked();
     put(e);
+    return save_locked();
+}
+
+int jevd_batch_tune_lookup(int size_class, int *waves, double *ms)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_loaded_locked();
+    for (const BatchTuneEntry &e : g_btab)
+        if (e.cls == size_class) {
+            if (waves) *waves = e.waves;
+            if (ms) *ms = e.ms;
+            return JEVD_OK;
+        }
+    return JEVD_EINVAL;
+}
+
+int jevd_batch_tune_record(int size_class, int waves, double ms)
+{
+    const BatchTuneEntry e{size_class, waves, ms};
+    if (!valid_batch_entry(e)) return JEVD_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    ensure_loaded_locked();
+    put_batch(e);
     return save_locked();
 }
 

@@ -23,7 +23,10 @@ EXPORTS = ("jevd_default_opts", "jevd_create", "jevd_destroy", "jacobi_evd", "je
            "jevd_batch_create", "jevd_batch_run", "jevd_batch_results", "jevd_batch_destroy",
            "jacobi_evd_batched", "jevd_canonicalize", "jevd_adjoint", "jevd_adjoint_noalloc",
            "jevd_autotune",
-           "jevd_tune_file", "jevd_tune_lookup", "jevd_tune_record", "jevd_mfma_f64_rate")
+           "jevd_tune_file", "jevd_tune_lookup", "jevd_tune_record", "jevd_mfma_f64_rate",
+           "jevd_batch_waves", "jevd_batch_autotune", "jevd_batch_tune_lookup",
+           "jevd_batch_tune_record")
+BATCH_CLASSES = 4
 K_PAIR_STEP, K_GRAM, K_PIVOT_SOLVE, K_UPDATE = 0, 1, 2, 3
 
 
@@ -94,6 +97,10 @@ def lib():
         L.jevd_tune_lookup.argtypes = [_i, _i, _ip, _ip, _dp]
         L.jevd_tune_record.argtypes = [_i, _i, _i, _i, ctypes.c_double]
         L.jevd_mfma_f64_rate.argtypes = [_vp, _i, _i, _dp]
+        L.jevd_batch_waves.argtypes = [_vp, _ip]
+        L.jevd_batch_autotune.argtypes = [_vp, _i, _ip]
+        L.jevd_batch_tune_lookup.argtypes = [_i, _ip, _dp]
+        L.jevd_batch_tune_record.argtypes = [_i, _i, ctypes.c_double]
         for name in EXPORTS:
             if name != "jevd_strerror":
                 getattr(L, name).restype = ctypes.c_int
@@ -197,6 +204,36 @@ def jevd_mfma_f64_rate(h, waves_per_simd=4, iters=2048):
     if st != JEVD_OK:
         raise JevdError(st, "jevd_mfma_f64_rate")
     return t.value
+
+
+def jevd_batch_waves(plan):
+    """Wavefronts per workgroup of each size class of a plan (0: empty)."""
+    w = (ctypes.c_int * BATCH_CLASSES)()
+    st = lib().jevd_batch_waves(plan, w)
+    if st != JEVD_OK:
+        raise JevdError(st, "jevd_batch_waves")
+    return list(w)
+
+
+def jevd_batch_autotune(h, want_v=True):
+    """Measures the batched solve's workgroup sizes per size class; returns
+    the choices (also recorded in the tune table)."""
+    w = (ctypes.c_int * BATCH_CLASSES)()
+    st = lib().jevd_batch_autotune(h, 1 if want_v else 0, w)
+    if st != JEVD_OK:
+        raise JevdError(st, "jevd_batch_autotune")
+    return list(w)
+
+
+def jevd_batch_tune_lookup(size_class):
+    """Returns (status, waves, ms) of the table's record for a size class."""
+    w, ms = ctypes.c_int(0), ctypes.c_double(0.0)
+    st = lib().jevd_batch_tune_lookup(int(size_class), ctypes.byref(w), ctypes.byref(ms))
+    return st, w.value, ms.value
+
+
+def jevd_batch_tune_record(size_class, waves, ms):
+    return lib().jevd_batch_tune_record(int(size_class), int(waves), float(ms))
 
 
 def jevd_ordering(n, ordering):

@@ -248,3 +248,38 @@ def test_mfma_rate_rejects_bad_arguments():
         assert L.jevd_mfma_f64_rate(fake, wps, iters, ctypes.byref(t)) == B.JEVD_EINVAL
     assert L.jevd_mfma_f64_rate(fake, 4, 16, None) == B.JEVD_EINVAL
     assert t.value == -1.0
+
+
+def test_batch_tune_table_record_lookup_and_file(tmp_path):
+    """The batched solve's per-class records: kept, looked up, written to
+    the table file beside the block records and read back; invalid records
+    refused."""
+    path = str(tmp_path / "tune.txt")
+    try:
+        assert B.jevd_tune_file(path) == B.JEVD_OK
+        assert B.jevd_batch_tune_lookup(0)[0] == B.JEVD_EINVAL
+        assert B.jevd_batch_tune_record(0, 4, 1.5) == B.JEVD_OK
+        assert B.jevd_batch_tune_record(2, 8, 7.25) == B.JEVD_OK
+        assert B.jevd_batch_tune_record(2, 16, 6.0) == B.JEVD_OK      # the last record wins
+        assert B.jevd_tune_record(512, 512, 32, 1, 3.0) == B.JEVD_OK  # a block record beside them
+        for bad in ((-1, 4, 1.0), (B.BATCH_CLASSES, 4, 1.0), (1, 3, 1.0), (1, 32, 1.0),
+                    (1, 8, -1.0)):
+            assert B.jevd_batch_tune_record(*bad) == B.JEVD_EINVAL, bad
+        text = open(path).read()
+        assert "batch 0 4 " in text and "batch 2 16 " in text and "batch 2 8 " not in text
+        assert B.jevd_tune_file(path) == B.JEVD_OK   # reload from the file
+        assert B.jevd_batch_tune_lookup(0)[:2] == (B.JEVD_OK, 4)
+        assert B.jevd_batch_tune_lookup(2)[:2] == (B.JEVD_OK, 16)
+        assert B.jevd_batch_tune_lookup(1)[0] == B.JEVD_EINVAL
+        assert B.jevd_tune_lookup(512, 512)[:3] == (B.JEVD_OK, 32, 1)
+    finally:
+        B.jevd_tune_file(None)
+
+
+def test_batch_tuning_entry_points_reject_bad_arguments():
+    L = B.lib()
+    w = (ctypes.c_int * B.BATCH_CLASSES)()
+    assert L.jevd_batch_waves(None, w) == B.JEVD_EINVAL
+    assert L.jevd_batch_autotune(None, 1, w) == B.JEVD_EINVAL
+    fake = ctypes.c_void_p(1)   # never dereferenced: the argument checks come first
+    assert L.jevd_batch_autotune(fake, 2, w) == B.JEVD_EINVAL

@@ -164,15 +164,27 @@ def test_batched_invalid_arguments(solver):
     assert e.value.status == jevd.JEVD_EINVAL
 
 
-def test_batched_plan_rerun_and_graph_replay(solver):
+@pytest.mark.parametrize("split", [False, True])
+def test_batched_plan_rerun_and_graph_replay(solver, split, tmp_path):
     """A plan rerun restarts from the current G_i; a captured plan replayed
     several times (with eager work between replays) gives the eager result
-    bit for bit on every replay."""
+    bit for bit on every replay.  split: the size classes run as three
+    launches (4, 8 and 16 wavefronts), two of them on the plan's second
+    stream, which the capture takes in through the fork and join events."""
     import torch
+    from paper_1008_0201_amd import jevd
     items = mixed_batch()[4:14]
     G0 = [dev_colmajor(G) for (G, J, tol, ld) in items]
     Gd = [x.clone() for x in G0]
-    plan = solver.batch_plan(Gd, [J for (G, J, tol, ld) in items], None, want_V=True)
+    if split:
+        assert jevd.jevd_tune_file(str(tmp_path / "tune.txt")) == jevd.JEVD_OK
+        for c, w in enumerate((4, 8, 16, 16)):
+            assert jevd.jevd_batch_tune_record(c, w, 1.0) == jevd.JEVD_OK
+    try:
+        plan = solver.batch_plan(Gd, [J for (G, J, tol, ld) in items], None, want_V=True)
+    finally:
+        jevd.jevd_tune_file(None)
+    assert jevd.jevd_batch_waves(plan.plan) == ([4, 8, 16, 16] if split else [16, 16, 16, 16])
     try:
         plan.run()
         st, sw_ref, stv = plan.results()
@@ -214,3 +226,47 @@ def test_batched_plan_rerun_and_graph_replay(solver):
         del graph
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("waves", [(4, 4, 4, 4), (8, 8, 8, 8), (16, 16, 16, 16), (4, 8, 16, 16),
+                                   (16, 8, 4, 16)])
+def test_batched_every_workgroup_size_matches_oracle(solver, orc, waves, tmp_path):
+    """The tune table's per-class workgroup sizes (class 0 .. 3): every size
+    the kernel is built for, alone or mixed over the classes (then one to
+    four launches on two streams), gives the oracle's results."""
+    from paper_1008_0201_amd import jevd
+    path = str(tmp_path / "tune.txt")
+    try:
+        assert jevd.jevd_tune_file(path) == jevd.JEVD_OK
+        for c in range(jevd.BATCH_CLASSES):
+            assert jevd.jevd_batch_tune_record(c, waves[c], 1.0) == jevd.JEVD_OK
+        items = mixed_batch()
+        plan = solver.batch_plan([dev_colmajor(G, ld) for (G, J, tol, ld) in items],
+                                 [J for (G, J, tol, ld) in items], [t for (G, J, t, ld) in items])
+        try:
+            got = jevd.jevd_batch_waves(plan.plan)
+        finally:
+            plan.close()
+        # every class's step arrays (n <= 300 here) fit the smallest LDS share
+        assert got == list(waves), got
+        res = run_batch(solver, items, W.MODMODULUS)
+    finally:
+        jevd.jevd_tune_file(None)
+    for i, ((G, J, tol, ld), r) in enumerate(zip(items, res)):
+        check_instance(orc, G, J, tol, W.MODMODULUS, r["lam"], r["U"], r["V"], r["G"], r["sweeps"],
+                       r["st"], "waves %s instance %d n=%d" % (waves, i, G.shape[1]))
+
+
+def test_batched_autotune_records_a_size_per_class(solver, tmp_path):
+    from paper_1008_0201_amd import jevd
+    path = str(tmp_path / "tune.txt")
+    try:
+        assert jevd.jevd_tune_file(path) == jevd.JEVD_OK
+        got = jevd.jevd_batch_autotune(solver.h)
+        assert len(got) == jevd.BATCH_CLASSES and all(w in (4, 8, 16) for w in got), got
+        for c, w in enumerate(got):
+            st, tw, ms = jevd.jevd_batch_tune_lookup(c)
+            assert st == jevd.JEVD_OK and tw == w and ms > 0.0, (c, st, tw, ms)
+        assert "batch 0 " in open(path).read()
+    finally:
+        jevd.jevd_tune_file(None)
