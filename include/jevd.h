@@ -51,7 +51,8 @@ enum {
 
 /* Pivot orderings (Sec. 2.4, Fig. 2-3, Alg. 3.1). */
 enum {
-    JEVD_ORD_ROWCYCLIC = 0,   /* (1,2),(1,3),...,(n-1,n): one pair at a time */
+    JEVD_ORD_ROWCYCLIC = 0,   /* (1,2),(1,3),...,(n-1,n); the result of one pair at a
+                                 time, run as the 2n - 3 steps of equal i + j */
     JEVD_ORD_MODULUS = 1,     /* step k: all pairs with i + j == k (mod n) */
     JEVD_ORD_MODMODULUS = 2   /* modulus plus the pair of the two idle indices on even steps (default) */
 };
@@ -386,7 +387,10 @@ const char *jevd_strerror(int status);
  * as 0-based pairs (i < j) grouped in steps, each step's pairs in the order
  * they are dealt to workgroups (for the modified modulus ordering on even n:
  * the processes of the ring of Alg. 3.1, arranged so that neighbouring
- * processes share an XCD).  step_start (nsteps + 1 ints)
+ * processes share an XCD; for the row-cyclic ordering: the 2n - 3 steps of
+ * pairs with equal i + j, i ascending, in which every column meets its
+ * pairs in row order, so that the steps give the result of the pairs one at
+ * a time).  step_start (nsteps + 1 ints)
  * and pairs (2 ints per pair) may be NULL to query sizes; *nsteps and
  * *npairs receive the counts.  Pairs of a step are disjoint.  No device work.
  */

@@ -423,7 +423,7 @@ static int run_pointwise(jevd_handle_t h, int m, int n, double *G, int ldg, cons
     int lg = 0, lv = 0;
     const bool small = small_solve_lds_bytes(m, n, V != nullptr, &lg, &lv) > 0 && lg &&
                        (V == nullptr || lv) && (o.ordering == JEVD_ORD_ROWCYCLIC || n <= 128);
-    if (o.ordering == JEVD_ORD_ROWCYCLIC || small) {
+    if (small) {
         // whole solve in one workgroup (all sweeps inside the kernel)
         HIP_TRY(hipMemsetAsync(h->dctr, 0, sizeof(SweepCounters) * o.max_sweeps, h->stream));
         SmallSolveArgs a{G, m, n, (long)ldg, V, (long)ldv, dJ, tol, h->dpairs, h->dstep, nsteps,

@@ -41,14 +41,6 @@ __host__ __device__ constexpr size_t batch_lds_bytes(int nw)
     return (kBatchLdsBytes * (size_t)nw / kBatchWaves) & ~(size_t)15;
 }
 
-// pairs of step st of the ordering over n columns (row-cyclic: one pair;
-// modulus family: closed form)
-__device__ __forceinline__ int batch_step_pairs(int ordering, int n, int st)
-{
-    if (ordering == kOrdRowCyclic) return 1;
-    return modulus_step_pairs(n, st + 1, ordering == kOrdModModulus);
-}
-
 // Per-instance context of one workgroup.
 struct InstCtx {
     int m, n;
@@ -421,10 +413,14 @@ __device__ __forceinline__ int sweep_instance(double *g, long ldg, double *v, lo
     while (sweep < max_sweeps) {
         unsigned rot = 0;
         if (ordering == kOrdRowCyclic) {
-            // one pair at a time, in wavefront 0 (no barrier between steps)
-            if (wave == 0)
-                for (int p = 0; p < n - 1; ++p)
-                    for (int q = p + 1; q < n; ++q) one_pair_loop(g, ldg, v, ldv, c, p, q, lane, rot, bad);
+            // the steps of equal p + q (the same result as one pair at a
+            // time in row order), a pair per wavefront
+            for (int t = 1; t <= rowcyclic_steps(n); ++t) {
+                const int p0 = rowcyclic_first(n, t), np = rowcyclic_step_pairs(n, t);
+                for (int e = wave; e < np; e += NW)
+                    one_pair_loop(g, ldg, v, ldv, c, p0 + e, t - p0 - e, lane, rot, bad);
+                __syncthreads();
+            }
         } else {
             const bool modified = ordering == kOrdModModulus;
             if constexpr (R > 0) {

@@ -11,7 +11,9 @@
 // for the modified modulus on even N the pairs of each step are listed in
 // the order of the ring's processes (see ring_schedule), permuted to
 // workgroup slots (see slot_process).
-// Row-cyclic: one pair per step, (1,2),(1,3),...,(1,N),(2,3),...,(N-1,N).
+// Row-cyclic: the pairs (1,2),(1,3),...,(1,N),(2,3),...,(N-1,N), run as the
+// 2N - 3 steps of equal i + j (rowcyclic_steps in ordering.h), which give the
+// same result as one pair at a time.
 #include <vector>
 
 #include "ordering.h"
@@ -80,12 +82,14 @@ int build_ordering(int n, int ordering, std::vector<int> &step_start, std::vecto
     pairs.clear();
     if (n < 1) return -1;
     if (ordering == kOrdRowCyclic) {
-        for (int i = 0; i < n; ++i)
-            for (int j = i + 1; j < n; ++j) {
-                step_start.push_back((int)pairs.size() / 2);
-                pairs.push_back(i);
-                pairs.push_back(j);
+        for (int t = 1; t <= rowcyclic_steps(n); ++t) {
+            step_start.push_back((int)pairs.size() / 2);
+            const int i0 = rowcyclic_first(n, t);
+            for (int r = 0; r < rowcyclic_step_pairs(n, t); ++r) {
+                pairs.push_back(i0 + r);
+                pairs.push_back(t - i0 - r);
             }
+        }
         step_start.push_back((int)pairs.size() / 2);
         return (int)step_start.size() - 1;
     }

@@ -45,4 +45,16 @@ JEVD_HD inline void modulus_pair(int N, int k, int r, int *i0, int *j0)
     *j0 = k / 2 + N / 2 - 1;
 }
 
+// Row-cyclic ordering (Sec. 2.4) as steps of disjoint pairs: step t =
+// 1 .. 2N - 3 holds the pairs (i, j), i < j, with i + j == t (0-based),
+// i = max(0, t - N + 1), ... .  Every pair that shares a column with (i, j)
+// and precedes it in row order, (i', i) and (i', j) with i' < i or (i, j')
+// with j' < j, has a smaller i + j, and every one that follows it a larger
+// one, so each column meets its transforms in row order with the same
+// operands; the transforms of one step touch disjoint columns and commute.
+// The result is that of the pairs taken one at a time in row order.
+JEVD_HD inline int rowcyclic_steps(int N) { return N >= 2 ? 2 * N - 3 : 0; }
+JEVD_HD inline int rowcyclic_first(int N, int t) { return t - N + 1 > 0 ? t - N + 1 : 0; }
+JEVD_HD inline int rowcyclic_step_pairs(int N, int t) { return (t + 1) / 2 - rowcyclic_first(N, t); }
+
 }  // namespace jevd

@@ -16,6 +16,7 @@
 //   k_identity, k_finalize  V := I; lambda_i = j_i ||g_i||^2, u_i = g_i / ||g_i||.
 #include "device_math.h"
 #include "jevd_internal.h"
+#include "ordering.h"
 
 namespace jevd {
 
@@ -528,16 +529,17 @@ __global__ __launch_bounds__(NW *kWave) void k_small_solve(
     if (threadIdx.x == 0) *sweeps_out = sweep;
 }
 
-// All sweeps of the row-cyclic ordering (the pairs (p, q), p < q, in row
-// order: strictly sequential) for m, n <= 64 in one wavefront, lane r holding
-// row r.  G and V sit in LDS column-major (pitch 64, rows past m or n zero).
-// The column p of the current row of pairs stays in registers for the whole
-// row; the next pair's column is read from LDS while the current pair is
-// transformed (it is not one of the pair's columns), so a pair's dependent
-// chain is its three dot products, their wavefront sums, the rotation
-// decision and transform, and the rotation.  The arithmetic is that of
-// small_pair (wave_sum, needs_rotation, transform_params, rotate_elems).
+// All sweeps of the row-cyclic ordering for m, n <= 64 in one workgroup.
+// The ordering runs as its 2n - 3 steps of equal p + q (rowcyclic_steps in
+// ordering.h: the result of one pair at a time in row order), the pairs of a
+// step side by side: each 16-lane row of a wavefront takes one pair, lane l
+// of the row holding rows l, l + 16, l + 32, l + 48 of its two columns of G
+// (and of V), so the Gram sums end in every lane of the row after four DPP
+// stages and a wavefront computes the transforms of four pairs at once.
+// G and V sit in LDS column-major (pitch 64, rows past m or n zero); NW
+// wavefronts cover the n / 2 pairs of the widest step.
 constexpr int kRowCyclicMax = 64;
+constexpr int kRcRows = 4;   // rows per lane
 
 // A DPP move of a double for patterns that have a source lane in every lane
 // (quad permutations, row mirrors): no old value is needed.
@@ -549,9 +551,11 @@ __device__ __forceinline__ double dpp_all(double v)
     return __hiloint2double(hi, lo);
 }
 
-// wave_sum of three values with the stages interleaved (the same additions
-// in the same order as wave_sum, so the same totals).
-__device__ __forceinline__ void wave_sum3(double &x, double &y, double &z)
+// Sums over the 16 lanes of each DPP row, three values with the stages
+// interleaved; every lane of the row ends with the row's totals (lane ^ 1,
+// lane ^ 2, then the mirrors within 8 and 16 lanes, each pairing a lane with
+// one of the other half).
+__device__ __forceinline__ void row_sum3(double &x, double &y, double &z)
 {
     x += dpp_all<0xB1>(x);
     y += dpp_all<0xB1>(y);
@@ -565,74 +569,117 @@ __device__ __forceinline__ void wave_sum3(double &x, double &y, double &z)
     x += dpp_all<0x140>(x);
     y += dpp_all<0x140>(y);
     z += dpp_all<0x140>(z);
-    const double x0 = read_lane(x, 0), x1 = read_lane(x, 16), x2 = read_lane(x, 32), x3 = read_lane(x, 48);
-    const double y0 = read_lane(y, 0), y1 = read_lane(y, 16), y2 = read_lane(y, 32), y3 = read_lane(y, 48);
-    const double z0 = read_lane(z, 0), z1 = read_lane(z, 16), z2 = read_lane(z, 32), z3 = read_lane(z, 48);
-    x = (x0 + x1) + (x2 + x3);
-    y = (y0 + y1) + (y2 + y3);
-    z = (z0 + z1) + (z2 + z3);
 }
 
-__global__ __launch_bounds__(kWave) void k_rowcyclic_solve(
+template <int NW>
+__global__ __launch_bounds__(NW *kWave) void k_rowcyclic_solve(
     double *__restrict__ G, int m, int n, long ldg, double *__restrict__ V, long ldv,
     const signed char *__restrict__ J, double tol, int max_sweeps,
     SweepCounters *__restrict__ ctr, int *__restrict__ sweeps_out)
 {
-    constexpr int P = kRowCyclicMax;
+    constexpr int P = kRowCyclicMax, BS = NW * kWave;
     __shared__ double g[P * P], v[P * P];
     __shared__ signed char js[P];
-    const int lane = threadIdx.x;
-    for (int c = 0; c < n; ++c) {
-        g[c * P + lane] = lane < m ? G[(size_t)c * ldg + lane] : 0.0;
-        v[c * P + lane] = (V && lane < n) ? V[(size_t)c * ldv + lane] : 0.0;
+    __shared__ unsigned long long red[3 * NW];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int grp = lane >> 4, l16 = lane & 15;
+    for (int e = tid; e < P * n; e += BS) {
+        const int c = e / P, r = e % P;
+        g[e] = r < m ? G[(size_t)c * ldg + r] : 0.0;
+        if (V) v[e] = r < n ? V[(size_t)c * ldv + r] : 0.0;
     }
-    if (lane < n) js[lane] = J ? J[lane] : (signed char)1;
+    if (tid < n) js[tid] = J ? J[tid] : (signed char)1;
     __syncthreads();
     int sweep = 0;
     while (sweep < max_sweeps) {
-        unsigned long long rot = 0, ncl = 0;
-        int nonfinite = 0;
-        for (int p = 0; p + 1 < n; ++p) {
-            double a = g[p * P + lane], va = v[p * P + lane];
-            double b = g[(p + 1) * P + lane], vb = v[(p + 1) * P + lane];
-            const signed char jp = js[p];
-            for (int q = p + 1; q < n; ++q) {
-                // the next pair's column (a repeat of column q on the last pair, unused)
-                const int qn = q + 1 < n ? q + 1 : q;
-                const double bn = g[qn * P + lane], vbn = v[qn * P + lane];
-                const bool same = jp == js[q];
-                double app = a * a, aqq = b * b, apq = a * b;
-                wave_sum3(app, aqq, apq);
-                if (!finite3(app, aqq, apq)) {
-                    nonfinite = 1;
-                } else if (needs_rotation(app, aqq, apq, tol)) {
-                    double c, s;
-                    ncl += transform_params(app, aqq, apq, same, c, s) ? 1 : 0;
-                    rotate_elems(a, b, c, s, same);
-                    rotate_elems(va, vb, c, s, same);
-                    g[q * P + lane] = b;
-                    v[q * P + lane] = vb;
-                    ++rot;
+        unsigned long long rot = 0, ncl = 0, nonfinite = 0;   // counted by lane 0 of a row
+        for (int t = 1; t <= rowcyclic_steps(n); ++t) {
+            const int p0 = rowcyclic_first(n, t), np = rowcyclic_step_pairs(n, t);
+            if (4 * wave < np) {
+                const int e = 4 * wave + grp;
+                const bool active = e < np;
+                const int p = active ? p0 + e : p0, q = t - p;   // a valid pair when idle
+                double x[kRcRows], y[kRcRows], vx[kRcRows], vy[kRcRows];
+#pragma unroll
+                for (int i = 0; i < kRcRows; ++i) {
+                    x[i] = g[p * P + 16 * i + l16];
+                    y[i] = g[q * P + 16 * i + l16];
                 }
-                b = bn;
-                vb = vbn;
+                if (V) {
+#pragma unroll
+                    for (int i = 0; i < kRcRows; ++i) {
+                        vx[i] = v[p * P + 16 * i + l16];
+                        vy[i] = v[q * P + 16 * i + l16];
+                    }
+                }
+                double app = 0.0, aqq = 0.0, apq = 0.0;
+#pragma unroll
+                for (int i = 0; i < kRcRows; ++i) {
+                    app = fma(x[i], x[i], app);
+                    aqq = fma(y[i], y[i], aqq);
+                    apq = fma(x[i], y[i], apq);
+                }
+                row_sum3(app, aqq, apq);
+                const bool fin = finite3(app, aqq, apq);
+                if (active && !fin && l16 == 0) nonfinite = 1;
+                if (active && fin && needs_rotation(app, aqq, apq, tol)) {
+                    const bool same = js[p] == js[q];
+                    double c, sn;
+                    const bool clamped = transform_params(app, aqq, apq, same, c, sn);
+#pragma unroll
+                    for (int i = 0; i < kRcRows; ++i) {
+                        rotate_elems(x[i], y[i], c, sn, same);
+                        g[p * P + 16 * i + l16] = x[i];
+                        g[q * P + 16 * i + l16] = y[i];
+                    }
+                    if (V) {
+#pragma unroll
+                        for (int i = 0; i < kRcRows; ++i) {
+                            rotate_elems(vx[i], vy[i], c, sn, same);
+                            v[p * P + 16 * i + l16] = vx[i];
+                            v[q * P + 16 * i + l16] = vy[i];
+                        }
+                    }
+                    if (l16 == 0) {
+                        ++rot;
+                        ncl += clamped ? 1 : 0;
+                    }
+                }
             }
-            g[p * P + lane] = a;
-            v[p * P + lane] = va;
+            if constexpr (NW > 1) __syncthreads();
         }
+        // totals over the rows of the wavefront, then over the wavefronts
+        const unsigned long long wr = __shfl(rot, 0) + __shfl(rot, 16) + __shfl(rot, 32) + __shfl(rot, 48);
+        const unsigned long long wc = __shfl(ncl, 0) + __shfl(ncl, 16) + __shfl(ncl, 32) + __shfl(ncl, 48);
+        const unsigned long long wn = __shfl(nonfinite, 0) | __shfl(nonfinite, 16) |
+                                      __shfl(nonfinite, 32) | __shfl(nonfinite, 48);
         if (lane == 0) {
-            ctr[sweep].rotations = rot;
-            ctr[sweep].clamps = ncl;
-            ctr[sweep].nonfinite = nonfinite;
+            red[wave] = wr;
+            red[NW + wave] = wc;
+            red[2 * NW + wave] = wn;
+        }
+        __syncthreads();
+        unsigned long long tr = 0, tc = 0, tn = 0;
+        for (int w = 0; w < NW; ++w) {
+            tr += red[w];
+            tc += red[NW + w];
+            tn |= red[2 * NW + w];
+        }
+        if (tid == 0) {
+            ctr[sweep].rotations = tr;
+            ctr[sweep].clamps = tc;
+            ctr[sweep].nonfinite = (int)tn;
         }
         ++sweep;
-        if (rot == 0 || nonfinite) break;
+        __syncthreads();   // red is rewritten by the next sweep
+        if (tr == 0 || tn) break;
     }
-    for (int c = 0; c < n; ++c) {
-        if (lane < m) G[(size_t)c * ldg + lane] = g[c * P + lane];
-        if (V && lane < n) V[(size_t)c * ldv + lane] = v[c * P + lane];
+    for (int e = tid; e < P * n; e += BS) {
+        const int c = e / P, r = e % P;
+        if (r < m) G[(size_t)c * ldg + r] = g[e];
+        if (V && r < n) V[(size_t)c * ldv + r] = v[e];
     }
-    if (lane == 0) *sweeps_out = sweep;
+    if (tid == 0) *sweeps_out = sweep;
 }
 
 __global__ void k_identity(double *__restrict__ V, int n, long ldv)
@@ -742,8 +789,20 @@ static hipError_t launch_small_nw(const SmallSolveArgs &a, hipStream_t st)
 hipError_t launch_small_solve(const SmallSolveArgs &a, hipStream_t st)
 {
     if (a.row_cyclic && a.m <= kRowCyclicMax && a.n <= kRowCyclicMax) {
-        k_rowcyclic_solve<<<1, kWave, 0, st>>>(a.G, a.m, a.n, a.ldg, a.V, a.ldv, a.J, a.tol,
-                                               a.max_sweeps, a.ctr, a.sweeps_out);
+        // four pairs per wavefront, n / 2 pairs in the widest step
+        const int waves = (a.n / 2 + 3) / 4;
+        if (waves <= 1)
+            k_rowcyclic_solve<1><<<1, kWave, 0, st>>>(a.G, a.m, a.n, a.ldg, a.V, a.ldv, a.J, a.tol,
+                                                      a.max_sweeps, a.ctr, a.sweeps_out);
+        else if (waves <= 2)
+            k_rowcyclic_solve<2><<<1, 2 * kWave, 0, st>>>(a.G, a.m, a.n, a.ldg, a.V, a.ldv, a.J,
+                                                          a.tol, a.max_sweeps, a.ctr, a.sweeps_out);
+        else if (waves <= 4)
+            k_rowcyclic_solve<4><<<1, 4 * kWave, 0, st>>>(a.G, a.m, a.n, a.ldg, a.V, a.ldv, a.J,
+                                                          a.tol, a.max_sweeps, a.ctr, a.sweeps_out);
+        else
+            k_rowcyclic_solve<8><<<1, 8 * kWave, 0, st>>>(a.G, a.m, a.n, a.ldg, a.V, a.ldv, a.J,
+                                                          a.tol, a.max_sweeps, a.ctr, a.sweeps_out);
         return hipGetLastError();
     }
     // one wavefront for strictly sequential orderings; otherwise up to 16

@@ -37,10 +37,8 @@ def test_strerror_and_defaults():
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 17, 64, 255, 256, 1024])
-@pytest.mark.parametrize("kind", [0, 1, 2])
+@pytest.mark.parametrize("kind", [1, 2])
 def test_library_ordering_matches_oracle(orc, n, kind):
-    if kind == 0 and n > 256:
-        pytest.skip("row-cyclic table is n^2/2 steps")
     lib_steps = B.jevd_ordering(n, kind)
     orc_steps = orc.ordering(n, kind)
     assert len(lib_steps) == len(orc_steps)

@@ -83,15 +83,20 @@ def test_small_spd_rowcyclic_n64(solver, orc):
 
 
 @pytest.mark.parametrize("m,n,ld,want_V", [(1, 1, None, True), (2, 2, None, True),
-                                            (5, 3, 9, True), (17, 17, None, False),
+                                            (3, 3, None, True), (5, 3, 9, True),
+                                            (9, 8, None, True), (17, 17, None, False),
                                             (40, 33, 41, True), (64, 50, None, True),
-                                            (64, 64, 70, True)])
+                                            (64, 64, 70, True), (64, 64, None, False),
+                                            (65, 65, None, True), (100, 90, None, True)])
 @pytest.mark.parametrize("indef", [False, True])
-def test_rowcyclic_one_wavefront(solver, orc, m, n, ld, want_V, indef):
-    """The row-cyclic ordering for m, n <= 64 (one wavefront, one row per
-    lane, the next pair's column read ahead): graded columns, odd and ragged
-    shapes, a padded leading dimension, with and without V, J = I and mixed
-    signs; eigenvalues, sweep count, U, V and G V against the oracle."""
+def test_rowcyclic_small(solver, orc, m, n, ld, want_V, indef):
+    """The row-cyclic ordering run as its steps of equal p + q in one
+    workgroup: for m, n <= 64 four pairs per wavefront (16 lanes a pair, 1,
+    2, 4 or 8 wavefronts), above that the step table of the general
+    single-workgroup solve.  Graded columns, odd and ragged shapes, a padded
+    leading dimension, with and without V, J = I and mixed signs;
+    eigenvalues, sweep count, U, V and G V against the oracle (one pair at a
+    time in row order)."""
     g = np.random.default_rng(3000 + 100 * m + n + 7 * indef)
     G = g.standard_normal((m, n)) * (10.0 ** g.uniform(-2, 2, size=n))[None, :]
     J = None
@@ -130,6 +135,8 @@ def test_pair_step_path(solver, orc, m, n, indef):
 
 @pytest.mark.parametrize("ordering", [W.MODULUS, W.ROWCYCLIC])
 def test_other_orderings(solver, orc, ordering):
+    """n = 150 with V does not fit one workgroup's LDS: one launch per step
+    (for row-cyclic the 297 steps of equal p + q)."""
     wl = W.graded_hyperbolic(150, k=31, grade=1.5)
     got = run_gpu(solver, wl.G, wl.J, wl.tol, ordering)
     check_against_oracle(orc, wl.G, wl.J, wl.tol, ordering, got)
