@@ -582,27 +582,191 @@ struct PivotSolveArgs {
 template <int W>
 constexpr int gram_pitch() { return W + 1; }
 
-// Workgroup of the pivot solve: 4 wavefronts.  In the inner sweeps lanes 2k
-// and 2k + 1 of every wavefront own pair k of the step (W/2 pairs), each half
-// of the wavefront's rows [w W/4, (w+1) W/4) of R and V_P: the two lanes
-// add their partial dot products (one DPP swap), the wavefronts' partials
-// meet in LDS, and every wavefront adds them in wavefront order (identical
-// totals everywhere) and computes the 2x2 transforms of all pairs at once
-// before each lane rotates its rows.
+// Workgroup of the pivot solve: 4 wavefronts; the inner sweeps run as
+// ring_sweep (each pair on 8 or 16 lanes of one wavefront).
 constexpr int kPivotThreads = 256;
+
+// Sum over groups of L consecutive lanes (L = 8 or 16); every lane of a
+// group ends with the group's total (lane ^ 1, lane ^ 2, then the mirrors
+// within 8 and 16 lanes, each pairing a lane with one of the other half).
+template <int L>
+__device__ __forceinline__ void group_sum3_all(double &x, double &y, double &z)
+{
+    static_assert(L == 8 || L == 16, "DPP groups of 8 or 16 lanes");
+    x += dpp_move<0xB1>(x);
+    y += dpp_move<0xB1>(y);
+    z += dpp_move<0xB1>(z);
+    x += dpp_move<0x4E>(x);
+    y += dpp_move<0x4E>(y);
+    z += dpp_move<0x4E>(z);
+    x += dpp_move<0x141>(x);
+    y += dpp_move<0x141>(y);
+    z += dpp_move<0x141>(z);
+    if constexpr (L == 16) {
+        x += dpp_move<0x140>(x);
+        y += dpp_move<0x140>(y);
+        z += dpp_move<0x140>(z);
+    }
+}
+
+// One inner sweep over the W columns of R (A) and V_P (VP), both in LDS at
+// pitch gram_pitch<W>, for W = 32 or 64 in the kPivotThreads workgroup.
+// The W/2 pairs of a step go to W/2 processes, PPW per wavefront, L lanes a
+// process; lane l of a process holds rows l, l + L, ... of the pair's two
+// columns of R and of V_P in registers.  From one step to the next a
+// process keeps one of its columns: in the ring of Alg. 3.1 (all pairs: the
+// modified modulus steps, process k starting on (k, W - 1 - k) and moving
+// by the process map) and in the bipartite shift (process k: column k of
+// block I, the J column moving on).  Only the column it gives up goes
+// through LDS: written after the step, read by the process that takes it
+// after the barrier, so a step moves half the columns and has one barrier.
+// The kept column stays in K (id ck), the received one in N (id cn); the
+// pair is (min, max) of the two ids.  On entry and exit every column is in
+// LDS.  Returns the rotations of the sweep counted once per pair (on lane 0
+// of each process).
+template <int W, bool ALL>
+__device__ __forceinline__ unsigned long long ring_sweep(double *A, double *VP,
+                                                         const signed char *JI, double tol,
+                                                         unsigned long long &ncl, int &bad)
+{
+    constexpr int P = gram_pitch<W>(), NW = kPivotThreads / 64, NP = W / 2;
+    constexpr int PPW = NP / NW, L = 64 / PPW, RL = W / L;
+    static_assert(PPW * NW == NP && L * RL == W, "pairs dealt evenly");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int k = wave * PPW + lane / L, lg = lane % L;
+    const int nsteps = inner_steps(ALL, W);
+    // ring state in the 1-based terms of the process map
+    int ra = k + 1, rc = W - k;
+    int ck = k, cn = ALL ? W - 1 - k : NP + k;
+    double K[RL], N[RL], VK[RL], VN[RL];
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+        K[i] = A[ck * P + lg + L * i];
+        N[i] = A[cn * P + lg + L * i];
+        VK[i] = VP[ck * P + lg + L * i];
+        VN[i] = VP[cn * P + lg + L * i];
+    }
+    unsigned long long rot = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        const bool kx = ck < cn;   // K holds the pair's first column
+        // this lane's products added as a pairwise tree (rounding grows with
+        // log2(RL), not RL), then over the lanes of the process
+        double tkk[RL], tnn[RL], tkn[RL];
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            tkk[i] = K[i] * K[i];
+            tnn[i] = N[i] * N[i];
+            tkn[i] = K[i] * N[i];
+        }
+#pragma unroll
+        for (int h = RL / 2; h > 0; h /= 2)
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+                tkk[i] += tkk[i + h];
+                tnn[i] += tnn[i + h];
+                tkn[i] += tkn[i + h];
+            }
+        double skk = tkk[0], snn = tnn[0], skn = tkn[0];
+        group_sum3_all<L>(skk, snn, skn);
+        const double app = kx ? skk : snn, aqq = kx ? snn : skk, apq = skn;
+        const int p = kx ? ck : cn, q = kx ? cn : ck;
+        // the threshold test and the transform in one branch-free chain
+        bool act;
+        double c, sn;
+        const bool same = JI[p] == JI[q];
+        const bool cl = rotation_params(app, aqq, apq, same, tol, act, c, sn);
+        if (!finite3(app, aqq, apq)) {
+            bad = 1;
+            act = false;
+        }
+        if (act) {
+            // rotate_elems on (x, y) = (K, N) or (N, K): K' = c K + al N,
+            // N' = c N + be K
+            const double al = same ? (kx ? -sn : sn) : sn;
+            const double be = same ? -al : sn;
+#pragma unroll
+            for (int i = 0; i < RL; ++i) {
+                const double k0 = K[i], n0 = N[i], vk0 = VK[i], vn0 = VN[i];
+                K[i] = c * k0 + al * n0;
+                N[i] = c * n0 + be * k0;
+                VK[i] = c * vk0 + al * vn0;
+                VN[i] = c * vn0 + be * vk0;
+            }
+            if (lg == 0) {
+                ++rot;
+                ncl += cl ? 1 : 0;
+            }
+        }
+        if (s + 1 == nsteps) break;
+        // the next pair of this process, the column it keeps and the one it
+        // receives
+        int pn, qn;
+        if constexpr (ALL) {
+            // moving down the first column becomes a (after the diagonal:
+            // the row no other process holds); walking right the second c
+            if (ra + rc > W) {
+                ++ra;
+                if (ra == rc) {
+                    ra -= NP;
+                    rc = ra;
+                }
+                pn = ra - 1;
+                qn = q;
+            } else {
+                ++rc;
+                pn = p;
+                qn = rc - 1;
+            }
+        } else {
+            pn = k;
+            qn = NP + (k + s + 1) % NP;
+        }
+        if (ck != pn && ck != qn) {
+            // N is the column kept: swap the roles
+#pragma unroll
+            for (int i = 0; i < RL; ++i) {
+                const double t = K[i], vt = VK[i];
+                K[i] = N[i];
+                VK[i] = VN[i];
+                N[i] = t;
+                VN[i] = vt;
+            }
+            const int t = ck;
+            ck = cn;
+            cn = t;
+        }
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            A[cn * P + lg + L * i] = N[i];
+            VP[cn * P + lg + L * i] = VN[i];
+        }
+        cn = (pn == ck) ? qn : pn;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RL; ++i) {
+            N[i] = A[cn * P + lg + L * i];
+            VN[i] = VP[cn * P + lg + L * i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RL; ++i) {
+        A[ck * P + lg + L * i] = K[i];
+        A[cn * P + lg + L * i] = N[i];
+        VP[ck * P + lg + L * i] = VK[i];
+        VP[cn * P + lg + L * i] = VN[i];
+    }
+    __syncthreads();
+    return rot;
+}
 
 template <int W>
 __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
 {
     constexpr int NW = kPivotThreads / 64;
     constexpr int P = gram_pitch<W>();
-    constexpr int NP = W / 2;          // pairs per inner step
-    constexpr int RPW = W / NW;        // rows of R / V_P per wavefront
-    static_assert(NP <= 32, "two lanes per pair");
     extern __shared__ double lds[];
     double *A = lds;                   // W x W column-major, pitch P: Gram, then R
     double *VP = lds + W * P;          // W x W column-major, pitch P (first: rows of R)
-    double *red = VP + W * P;          // NW x 3 x NP partial dot products
     __shared__ signed char JP[W], JS[W];
     __shared__ int s_piv[W], s_perm[W];
     __shared__ int s_need, s_bad, s_npos;
@@ -793,104 +957,11 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     }
     __syncthreads();
     const int sweeps = a.full_block ? a.max_inner : 1;
-    constexpr int HR = RPW / 2;                 // rows per lane in an inner step
-    const int pk = lane >> 1, half = lane & 1;  // the lane's pair and half
-    const int r0h = wave * RPW + half * HR;
     for (int it = 0; it < sweeps; ++it) {
         unsigned long long rot_it = 0;
         if (!broke) {
-            const int nsteps = inner_steps(a.all_pairs, W);
-            for (int s = 0; s < nsteps; ++s) {
-                // two lanes per pair: lane 2k + h takes rows [h HR, (h+1) HR)
-                // of this wavefront's rows of pair k
-                const bool mine = pk < NP;
-                int2 pq = make_int2(0, 1);
-                if (mine) pq = inner_pair(a.all_pairs, W, s, pk);
-                double *yp = A + pq.x * P + r0h, *yq = A + pq.y * P + r0h;
-                // this lane's rows of the pair stay in registers until the
-                // rotation (no other lane touches them in the step)
-                double xr[HR], yr[HR];
-#pragma unroll
-                for (int r = 0; r < HR; ++r) {
-                    xr[r] = yp[r];
-                    yr[r] = yq[r];
-                }
-                // partial dot products over this lane's rows, added as a
-                // pairwise tree (rounding grows with log2(HR), not HR), then
-                // the two lanes of the pair add theirs (x + y = y + x: both
-                // lanes hold the same sum)
-                double sxx[HR], syy[HR], sxy[HR];
-#pragma unroll
-                for (int r = 0; r < HR; ++r) {
-                    sxx[r] = xr[r] * xr[r];
-                    syy[r] = yr[r] * yr[r];
-                    sxy[r] = xr[r] * yr[r];
-                }
-#pragma unroll
-                for (int h = HR / 2; h > 0; h /= 2)
-#pragma unroll
-                    for (int r = 0; r < h; ++r) {
-                        sxx[r] += sxx[r + h];
-                        syy[r] += syy[r + h];
-                        sxy[r] += sxy[r + h];
-                    }
-                double app = sxx[0] + dpp_move<0xB1>(sxx[0]);
-                double aqq = syy[0] + dpp_move<0xB1>(syy[0]);
-                double apq = sxy[0] + dpp_move<0xB1>(sxy[0]);
-                if (mine && half == 0) {
-                    red[(wave * 3 + 0) * NP + pk] = app;
-                    red[(wave * 3 + 1) * NP + pk] = aqq;
-                    red[(wave * 3 + 2) * NP + pk] = apq;
-                }
-                __syncthreads();
-                app = aqq = apq = 0.0;
-                if (mine) {
-                    // (w0 + w1) + (w2 + w3): the same order in every wavefront
-                    static_assert(NW == 4, "four wavefronts");
-                    double t[3][NW];
-#pragma unroll
-                    for (int w = 0; w < NW; ++w)
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) t[k][w] = red[(w * 3 + k) * NP + pk];
-                    app = (t[0][0] + t[0][1]) + (t[0][2] + t[0][3]);
-                    aqq = (t[1][0] + t[1][1]) + (t[1][2] + t[1][3]);
-                    apq = (t[2][0] + t[2][1]) + (t[2][2] + t[2][3]);
-                }
-                bool act = mine;
-                if (act && !finite3(app, aqq, apq)) {
-                    bad = 1;
-                    act = false;
-                }
-                act = act && needs_rotation(app, aqq, apq, a.tol);
-                const bool same = act ? (JI[pq.x] == JI[pq.y]) : true;
-                double c = 1.0, sn = 0.0;
-                if (act && transform_params(app, aqq, apq, same, c, sn) && wave == 0 && half == 0) ++ncl;
-                if (act) {
-                    // all loads first, then the arithmetic, then the stores:
-                    // one LDS latency instead of one per row
-                    double *vp = VP + pq.x * P + r0h, *vq = VP + pq.y * P + r0h;
-                    double vx[HR], vy[HR];
-#pragma unroll
-                    for (int r = 0; r < HR; ++r) {
-                        vx[r] = vp[r];
-                        vy[r] = vq[r];
-                    }
-#pragma unroll
-                    for (int r = 0; r < HR; ++r) {
-                        rotate_elems(xr[r], yr[r], c, sn, same);
-                        rotate_elems(vx[r], vy[r], c, sn, same);
-                    }
-#pragma unroll
-                    for (int r = 0; r < HR; ++r) {
-                        yp[r] = xr[r];
-                        yq[r] = yr[r];
-                        vp[r] = vx[r];
-                        vq[r] = vy[r];
-                    }
-                    if (wave == 0 && half == 0) ++rot_it;
-                }
-                __syncthreads();
-            }
+            rot_it = a.all_pairs ? ring_sweep<W, true>(A, VP, JI, a.tol, ncl, bad)
+                                 : ring_sweep<W, false>(A, VP, JI, a.tol, ncl, bad);
         } else {
             // G_P is transformed in place; V_P collects the transforms for V
             inner_sweep_global<NW>(a.G, a.ldg, a.m, VP, P, W, JP, a.all_pairs, W, a.tol, d, b,
@@ -2004,7 +2075,7 @@ static int prepare_tables(BlockWorkspace *ws, int n, int b, hipStream_t st)
 
 static size_t pivot_lds_bytes(int W)
 {
-    return (2 * (size_t)W * (W + 1) + 3 * (size_t)(kPivotThreads / 64) * (W / 2)) * sizeof(double);
+    return 2 * (size_t)W * (W + 1) * sizeof(double);
 }
 
 // Entries of the inner-transform log of one pivot (W = 128): one per pair

@@ -70,6 +70,31 @@ __device__ __forceinline__ bool needs_rotation(double app, double aqq, double ap
     return fabs(apq) > tol * sqrt(app) * sqrt(aqq);
 }
 
+// needs_rotation and transform_params in one branch-free chain, for
+// wavefronts whose lanes take different cases (trigonometric and hyperbolic
+// pairs, |zeta| past 1e150, the clamp): each case's expression is selected
+// as an operand instead of run as a branch of its own, so the wavefront
+// runs one division -> square root -> division -> square root -> division
+// chain with the threshold's square roots beside it.  The values are those
+// of needs_rotation and transform_params (the same expressions, chosen by
+// the same conditions); c and s are meaningless where need is false.
+__device__ __forceinline__ bool rotation_params(double app, double aqq, double apq, bool same_sign,
+                                                double tol, bool &need, double &c, double &s)
+{
+    need = app != 0.0 && aqq != 0.0 && fabs(apq) > tol * sqrt(app) * sqrt(aqq);
+    const double z = (same_sign ? aqq - app : app + aqq) / (2.0 * apq);
+    const double az = fabs(z);
+    const double sg = (z >= 0.0) ? 1.0 : -1.0;
+    const double rad = same_sign ? 1.0 + z * z : (az - 1.0) * (az + 1.0);
+    double t = (same_sign ? sg : -sg) / (az + sqrt(rad));
+    t = (az > 1e150) ? (same_sign ? 1.0 : -1.0) / (2.0 * z) : t;
+    const bool clamped = !same_sign && az <= 1.0;
+    t = clamped ? -sg * 0.9 : t;
+    c = 1.0 / sqrt(same_sign ? 1.0 + t * t : (1.0 - t) * (1.0 + t));
+    s = c * t;
+    return clamped;
+}
+
 __device__ __forceinline__ bool finite3(double a, double b, double c)
 {
     return isfinite(a) && isfinite(b) && isfinite(c);
