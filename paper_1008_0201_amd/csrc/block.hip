@@ -609,6 +609,22 @@ __device__ __forceinline__ void group_sum3_all(double &x, double &y, double &z)
     }
 }
 
+// The products x_i y_i of RL rows added as a pairwise tree (t_i += t_{i+h},
+// h = RL/2, ..., 1), rounded at every operation (no contraction), so that
+// ring_converged forms bit for bit the sums of a ring_sweep step.
+template <int RL>
+__device__ __forceinline__ double lane_dot(const double (&x)[RL], const double (&y)[RL])
+{
+    double t[RL];
+#pragma unroll
+    for (int i = 0; i < RL; ++i) t[i] = __dmul_rn(x[i], y[i]);
+#pragma unroll
+    for (int h = RL / 2; h > 0; h /= 2)
+#pragma unroll
+        for (int i = 0; i < h; ++i) t[i] = __dadd_rn(t[i], t[i + h]);
+    return t[0];
+}
+
 // One inner sweep over the W columns of R (A) and V_P (VP), both in LDS at
 // pitch gram_pitch<W>, for W = 32 or 64 in the kPivotThreads workgroup.
 // The W/2 pairs of a step go to W/2 processes, PPW per wavefront, L lanes a
@@ -651,22 +667,7 @@ __device__ __forceinline__ unsigned long long ring_sweep(double *A, double *VP,
         const bool kx = ck < cn;   // K holds the pair's first column
         // this lane's products added as a pairwise tree (rounding grows with
         // log2(RL), not RL), then over the lanes of the process
-        double tkk[RL], tnn[RL], tkn[RL];
-#pragma unroll
-        for (int i = 0; i < RL; ++i) {
-            tkk[i] = K[i] * K[i];
-            tnn[i] = N[i] * N[i];
-            tkn[i] = K[i] * N[i];
-        }
-#pragma unroll
-        for (int h = RL / 2; h > 0; h /= 2)
-#pragma unroll
-            for (int i = 0; i < h; ++i) {
-                tkk[i] += tkk[i + h];
-                tnn[i] += tnn[i + h];
-                tkn[i] += tkn[i + h];
-            }
-        double skk = tkk[0], snn = tnn[0], skn = tkn[0];
+        double skk = lane_dot<RL>(K, K), snn = lane_dot<RL>(N, N), skn = lane_dot<RL>(K, N);
         group_sum3_all<L>(skk, snn, skn);
         const double app = kx ? skk : snn, aqq = kx ? snn : skk, apq = skn;
         const int p = kx ? ck : cn, q = kx ? cn : ck;
@@ -759,6 +760,64 @@ __device__ __forceinline__ unsigned long long ring_sweep(double *A, double *VP,
     return rot;
 }
 
+// Whether an inner sweep run now would rotate nothing (full block: the
+// sweep that ends a pivot's inner iteration).  While no pair rotates the
+// columns do not change, so that sweep rotates nothing exactly when no pair
+// passes the threshold with the columns as they are; this tests all W (W-1)
+// / 2 pairs at once, one thread per pair, with the sums of a ring_sweep
+// step formed in the same order: lane l of a process (L lanes) holds rows l,
+// l + L, ... and adds its products by lane_dot; the DPP butterfly of
+// group_sum3_all then gives every lane the balanced tree over the lanes in
+// order, ((x0 + x1) + (x2 + x3)) + ((x4 + x5) + (x6 + x7)) (and the same for
+// lanes 8..15 added to it when L = 16), since a + b == b + a exactly.
+// Returns false as well when a sum is not finite (the sweep reports it).
+// Called by the whole workgroup; flag is a shared int.
+template <int W>
+__device__ bool ring_converged(const double *A, double tol, int *flag)
+{
+    constexpr int P = gram_pitch<W>(), NW = kPivotThreads / 64, NP = W / 2;
+    constexpr int PPW = NP / NW, L = 64 / PPW, RL = W / L;
+    if (threadIdx.x == 0) *flag = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < W * (W - 1) / 2; e += kPivotThreads) {
+        // pair e -> (p, q), p < q, by rows of the strict upper triangle
+        int p = 0, rem = e;
+        while (rem >= W - 1 - p) {
+            rem -= W - 1 - p;
+            ++p;
+        }
+        const int q = p + 1 + rem;
+        const double *cp = A + p * P, *cq = A + q * P;
+        double xpp[L], xqq[L], xpq[L];
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            double vp[RL], vq[RL];
+#pragma unroll
+            for (int i = 0; i < RL; ++i) {
+                vp[i] = cp[l + L * i];
+                vq[i] = cq[l + L * i];
+            }
+            xpp[l] = lane_dot<RL>(vp, vp);
+            xqq[l] = lane_dot<RL>(vq, vq);
+            xpq[l] = lane_dot<RL>(vp, vq);
+        }
+#pragma unroll
+        for (int h = 1; h < L; h *= 2)
+#pragma unroll
+            for (int l = 0; l < L; l += 2 * h) {
+                xpp[l] = __dadd_rn(xpp[l], xpp[l + h]);
+                xqq[l] = __dadd_rn(xqq[l], xqq[l + h]);
+                xpq[l] = __dadd_rn(xpq[l], xpq[l + h]);
+            }
+        const double app = xpp[0], aqq = xqq[0], apq = xpq[0];
+        if (!finite3(app, aqq, apq) || needs_rotation(app, aqq, apq, tol)) *flag = 1;
+    }
+    __syncthreads();
+    const bool conv = *flag == 0;
+    __syncthreads();
+    return conv;
+}
+
 template <int W>
 __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
 {
@@ -769,7 +828,7 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
     double *VP = lds + W * P;          // W x W column-major, pitch P (first: rows of R)
     __shared__ signed char JP[W], JS[W];
     __shared__ int s_piv[W], s_perm[W];
-    __shared__ int s_need, s_bad, s_npos;
+    __shared__ int s_need, s_bad, s_npos, s_conv;
     __shared__ unsigned long long s_rot[NW], s_cl[NW];
     const int pv = blockIdx.x;
     const int4 d = a.piv[pv];
@@ -977,6 +1036,9 @@ __global__ __launch_bounds__(kPivotThreads) void k_pivot_solve(PivotSolveArgs a)
         for (int w = 0; w < NW; ++w) tot += s_rot[w];
         __syncthreads();
         if (tot == 0) break;
+        // after a sweep with few rotations the next one usually rotates
+        // nothing: test that at once instead of running it
+        if (!broke && it + 1 < sweeps && tot <= W && ring_converged<W>(A, a.tol, &s_conv)) break;
     }
     {
         const double wr = wave_sum((double)rot), wc = wave_sum((double)ncl);
