@@ -14,7 +14,10 @@
 // which the 256 MiB Infinity Cache keeps on chip).  The eigenvalues
 // lambda_i and the normalised columns U_i are formed at the end of the
 // instance.
+#include <mutex>
+
 #include "../../include/jevd.h"
+
 #include "device_math.h"
 #include "jevd_internal.h"
 #include "ordering.h"
@@ -142,7 +145,8 @@ __device__ __forceinline__ void modulus_step(double *g, long ldg, double *v, lon
             modulus_pair(n, k, e, &p, &q);
             const bool same = c.J[p] == c.J[q];
             double cs, sn;
-            transform_params(app, aqq, apq, same, cs, sn);
+            // one lane per pair: pairs of both signs share the wavefront
+            transform_params_bf(app, aqq, apq, same, cs, sn);
             c.rotcs[2 * e] = cs;
             c.rotcs[2 * e + 1] = sn;
             f = same ? 1 : 2;
@@ -607,7 +611,9 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) vo
 
 __global__ void k_reset_queue(int *queue) { *queue = 0; }
 
-hipError_t prepare_batch_kernel()
+// The LDS limits are set once per device (a plan is created per call by
+// some callers, and the attribute calls cost about a millisecond each).
+static hipError_t set_batch_lds_limits()
 {
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void *)k_batch_solve<4>,
@@ -621,6 +627,20 @@ hipError_t prepare_batch_kernel()
     return hipFuncSetAttribute((const void *)k_batch_solve<16>,
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)batch_lds_bytes(16));
+}
+
+hipError_t prepare_batch_kernel()
+{
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev >= 0 && dev < 64 && done[dev]) return hipSuccess;
+    if ((e = set_batch_lds_limits()) != hipSuccess) return e;
+    if (dev >= 0 && dev < 64) done[dev] = true;
+    return hipSuccess;
 }
 
 bool batch_waves_supported(int waves) { return waves == 4 || waves == 8 || waves == 16; }

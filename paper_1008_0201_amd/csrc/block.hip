@@ -671,16 +671,16 @@ __device__ __forceinline__ unsigned long long ring_sweep(double *A, double *VP,
         group_sum3_all<L>(skk, snn, skn);
         const double app = kx ? skk : snn, aqq = kx ? snn : skk, apq = skn;
         const int p = kx ? ck : cn, q = kx ? cn : ck;
-        // the threshold test and the transform in one branch-free chain
-        bool act;
-        double c, sn;
-        const bool same = JI[p] == JI[q];
-        const bool cl = rotation_params(app, aqq, apq, same, tol, act, c, sn);
-        if (!finite3(app, aqq, apq)) {
+        bool act = false;
+        if (!finite3(app, aqq, apq))
             bad = 1;
-            act = false;
-        }
+        else
+            act = needs_rotation(app, aqq, apq, tol);
         if (act) {
+            // pairs of both signs may share the wavefront (sign pivoting)
+            const bool same = JI[p] == JI[q];
+            double c, sn;
+            const bool cl = transform_params_bf(app, aqq, apq, same, c, sn);
             // rotate_elems on (x, y) = (K, N) or (N, K): K' = c K + al N,
             // N' = c N + be K
             const double al = same ? (kx ? -sn : sn) : sn;

@@ -70,18 +70,17 @@ __device__ __forceinline__ bool needs_rotation(double app, double aqq, double ap
     return fabs(apq) > tol * sqrt(app) * sqrt(aqq);
 }
 
-// needs_rotation and transform_params in one branch-free chain, for
-// wavefronts whose lanes take different cases (trigonometric and hyperbolic
-// pairs, |zeta| past 1e150, the clamp): each case's expression is selected
-// as an operand instead of run as a branch of its own, so the wavefront
-// runs one division -> square root -> division -> square root -> division
-// chain with the threshold's square roots beside it.  The values are those
-// of needs_rotation and transform_params (the same expressions, chosen by
-// the same conditions); c and s are meaningless where need is false.
-__device__ __forceinline__ bool rotation_params(double app, double aqq, double apq, bool same_sign,
-                                                double tol, bool &need, double &c, double &s)
+// transform_params as one branch-free chain, for wavefronts whose lanes
+// take different cases (trigonometric and hyperbolic pairs, |zeta| past
+// 1e150, the clamp): each case's expression is selected as an operand
+// instead of run as a branch of its own, so the wavefront runs one division
+// -> square root -> division -> square root -> division chain instead of
+// one per case.  The values are those of transform_params (the same
+// expressions, chosen by the same conditions).  Callers test needs_rotation
+// first and skip this when no lane of the wavefront needs a transform.
+__device__ __forceinline__ bool transform_params_bf(double app, double aqq, double apq,
+                                                    bool same_sign, double &c, double &s)
 {
-    need = app != 0.0 && aqq != 0.0 && fabs(apq) > tol * sqrt(app) * sqrt(aqq);
     const double z = (same_sign ? aqq - app : app + aqq) / (2.0 * apq);
     const double az = fabs(z);
     const double sg = (z >= 0.0) ? 1.0 : -1.0;

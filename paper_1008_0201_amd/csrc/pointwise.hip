@@ -623,9 +623,10 @@ __global__ __launch_bounds__(NW *kWave) void k_rowcyclic_solve(
                 const bool fin = finite3(app, aqq, apq);
                 if (active && !fin && l16 == 0) nonfinite = 1;
                 if (active && fin && needs_rotation(app, aqq, apq, tol)) {
+                    // pairs of both signs may share the wavefront
                     const bool same = js[p] == js[q];
                     double c, sn;
-                    const bool clamped = transform_params(app, aqq, apq, same, c, sn);
+                    const bool clamped = transform_params_bf(app, aqq, apq, same, c, sn);
 #pragma unroll
                     for (int i = 0; i < kRcRows; ++i) {
                         rotate_elems(x[i], y[i], c, sn, same);
