@@ -2346,10 +2346,7 @@ static int prepare_steps(BlockWorkspace *ws, const BlockRunArgs &a, long ldg, bo
             HIP_TRY(hipEventCreateWithFlags(&ws->evVdone[i], hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&ws->evJoin, hipEventDisableTiming));
     }
-    if (W == 64)
-        HIP_TRY(hipFuncSetAttribute((const void *)k_pivot_solve<64>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)pivot_lds_bytes(64)));
+    if (W == 64) HIP_TRY(set_lds_limit((const void *)k_pivot_solve<64>, (int)pivot_lds_bytes(64)));
     *nsplit_out = nsplit;
     *rows_per_split_out = rows_per_split;
     return JEVD_OK;

@@ -175,7 +175,12 @@ hipError_t launch_adjoint(int batch, int m, int n, const double *G, int ldg, lon
                           long long sd, double *wsK, double *wsW, double *wsM, double *wsT,
                           hipStream_t st);
 constexpr int kBatchMaxN = 4096;   // largest n_i of a batched solve
-hipError_t prepare_batch_kernel();  // once before the first launch (sets the LDS limit)
+hipError_t prepare_batch_kernel();
+// hipFuncSetAttribute(func, MaxDynamicSharedMemorySize, bytes) on the current
+// device unless a limit of at least bytes was set there already (the call
+// costs about a millisecond; launches that need more than 64 KiB of dynamic
+// LDS call this before every launch).
+hipError_t set_lds_limit(const void *func, int bytes);  // once before the first launch (sets the LDS limit)
 hipError_t launch_batch(const BatchInst *inst, const int *order, int batch, int *queue,
                         int ordering, int max_sweeps, int accumulate_v, int *sweeps, int *status,
                         int grid, int waves, hipStream_t st);

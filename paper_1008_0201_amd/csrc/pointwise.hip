@@ -14,6 +14,8 @@
 //                      row-cyclic ordering, whose pairs are strictly
 //                      sequential, and for small n.
 //   k_identity, k_finalize  V := I; lambda_i = j_i ||g_i||^2, u_i = g_i / ||g_i||.
+#include <map>
+#include <mutex>
 #include "device_math.h"
 #include "jevd_internal.h"
 #include "ordering.h"
@@ -771,14 +773,29 @@ size_t small_solve_lds_bytes(int m, int n, bool want_v, int *lds_g, int *lds_v)
     return 0;
 }
 
+hipError_t set_lds_limit(const void *func, int bytes)
+{
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> set;   // (kernel, device) -> bytes
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = set.find({func, dev});
+    if (it != set.end() && it->second >= bytes) return hipSuccess;
+    if ((e = hipFuncSetAttribute(func, hipFuncAttributeMaxDynamicSharedMemorySize, bytes)) != hipSuccess)
+        return e;
+    set[{func, dev}] = bytes;
+    return hipSuccess;
+}
+
 template <int NW>
 static hipError_t launch_small_nw(const SmallSolveArgs &a, hipStream_t st)
 {
     int lg = 0, lv = 0;
     const size_t bytes = small_solve_lds_bytes(a.m, a.n, a.V != nullptr, &lg, &lv);
     if (bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_small_solve<NW>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        hipError_t e = set_lds_limit((const void *)k_small_solve<NW>, (int)bytes);
         if (e != hipSuccess) return e;
     }
     k_small_solve<NW><<<1, NW * kWave, bytes, st>>>(a.G, a.m, a.n, a.ldg, a.V, a.ldv, a.J, a.tol,
@@ -827,8 +844,7 @@ static hipError_t launch_apply_rb(const VlogApplyArgs &a, hipStream_t st)
                          (size_t)(a.k1 - a.k0 + 1) * sizeof(int);
     if (bytes > 160 * 1024) return hipErrorInvalidValue;
     if (bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_apply_vlog<RB, PPT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        hipError_t e = set_lds_limit((const void *)k_apply_vlog<RB, PPT>, (int)bytes);
         if (e != hipSuccess) return e;
     }
     const int grid = (a.nv + RB - 1) / RB;
