@@ -58,6 +58,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6
 FP32_MFMA_PEAK_TFS = 157.3
+FP64_VECTOR_PEAK_TFS = 78.6
 
 
 def pairs_per_sweep(n, ordering):
@@ -271,6 +272,12 @@ def run_batched(args):
                 "kernel": "k_batch_solve",
                 "avg_launch_us": round(kern_ms * 1e3, 1), "bytes_per_launch": hbm,
                 "flops_per_launch": work, "fp64_vector_tflops": round(achieved, 3),
+                # the bound the plan set for this workload (instances on chip):
+                # FP64 vector ALU; the kernel as built streams the larger
+                # instances from HBM, which is what binds it
+                "fp64_vector_bound": {"achieved": round(achieved, 3), "peak": FP64_VECTOR_PEAK_TFS,
+                                      "unit": "TFLOP/s",
+                                      "frac": round(achieved / FP64_VECTOR_PEAK_TFS, 4)},
                 "timing": "HIP events around jevd_batch_run on the solver stream (per launch "
                           "group a queue reset + one persistent launch; groups after the "
                           "first run at the same time on the plan's second stream)",
