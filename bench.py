@@ -693,20 +693,25 @@ def main():
     if not block and wl.ordering != 0 and kl[0]:
         # nominal pair-stream bytes per launch: 32 m bytes per pair for G, and
         # 32 n for V rotated in the step or 16 for its rotation-log entry
-        pairs_per_launch = P / n
+        # (a launch runs info.steps_per_launch steps: two for the ring of
+        # Alg. 3.1 when n is a multiple of 4 and 512 < m <= 1024)
+        spl = max(1, info.steps_per_launch)
+        kname = "k_pair_steps_ring" if spl > 1 else "k_pair_step"
+        pairs_per_launch = spl * P / n
         avg_ms = kms[0] / kl[0]
         deferred = info.v_deferred
         bytes_per_launch = pairs_per_launch * (32.0 * m + (16.0 if deferred else 32.0 * n))
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic("k_pair_step", wl.name),
-                    "kernel": "k_pair_step", "avg_launch_us": round(avg_ms * 1e3, 3),
+                    "traffic": measured_traffic(kname, wl.name),
+                    "kernel": kname, "steps_per_launch": spl,
+                    "avg_launch_us": round(avg_ms * 1e3, 3),
                     "bytes_per_launch": bytes_per_launch,
                     "timing": "HIP events around each sweep's launches on the solver stream; "
                               "average includes dispatch gaps"}
         if deferred and kl[3]:
-            kernels = {"k_pair_step": {"ms_per_solve": round(kms[0] / KSOLVES, 3),
+            kernels = {kname: {"ms_per_solve": round(kms[0] / KSOLVES, 3),
                                        "launches_per_solve": kl[0] // KSOLVES,
                                        "avg_us": round(1e3 * kms[0] / kl[0], 3)},
                        "k_apply_vlog": {"ms_per_solve": round(kms[3] / KSOLVES, 3),

@@ -136,6 +136,12 @@ typedef struct {
     int v_deferred;    /* pointwise with V: 1 when the steps logged their rotations
                           and V was updated from the log (timed as JEVD_K_UPDATE),
                           0 when each step rotated its two columns of V */
+    int steps_per_launch;  /* pointwise, one launch per step (not the single-
+                              workgroup solve): steps of the ordering per launch,
+                              1, or 2 for the ring of Alg. 3.1 (modified
+                              modulus, n a multiple of 4, 512 < m <= 1024),
+                              whose launches give the same bits as one step
+                              each */
 } jevd_info;
 
 /* Fills *o with the defaults listed above.  Never fails for a non-NULL o. */

@@ -106,6 +106,8 @@ struct jevd_handle_s {
     size_t capSlots = 0;
     double2 *dvlog = nullptr;    // pointwise rotation log (deferred V update), two buffers
     size_t capVlog = 0;
+    double *dgalt = nullptr;     // second copy of G for the multi-step ring launches
+    size_t capGalt = 0;
     hipStream_t vstream = nullptr;   // second stream of the deferred V update
     hipEvent_t evLogged[2] = {nullptr, nullptr};    // a log buffer is complete
     hipEvent_t evApplied[2] = {nullptr, nullptr};   // V is updated from a log buffer
@@ -328,6 +330,7 @@ int jevd_destroy(jevd_handle_t h)
     if (h->dstep) (void)hipFree(h->dstep);
     if (h->dslots) (void)hipFree(h->dslots);
     if (h->dvlog) (void)hipFree(h->dvlog);
+    if (h->dgalt) (void)hipFree(h->dgalt);
     if (h->vstream) {
         (void)hipStreamSynchronize(h->vstream);
         (void)hipStreamDestroy(h->vstream);
@@ -462,11 +465,33 @@ static int run_pointwise(jevd_handle_t h, int m, int n, double *G, int ldg, cons
     // Every exit joins the second stream into the handle's stream.
     const bool defer_v = V && vlog_rows(n) > 0 && nslots <= 16 * 256;
     h->info.v_deferred = defer_v ? 1 : 0;
+    // Two steps per launch (the ring of Alg. 3.1 on even n, each workgroup
+    // also running the process after its own): the modified modulus table
+    // of the ring, m small enough for one group of 256 threads per pair, V
+    // left to the log; the sweep's launches alternate between G and a second
+    // copy of it, an even number of them per sweep.  Measured at n = 1024:
+    // 61.0 ms with one step per launch, 58.0 with two, 71.8 with four (the
+    // recomputed processes, 2.5 times the pair work, cost more than the
+    // launches saved).
+    int ring_steps = 1;
+    // (m > 512: the rows per thread and block reduction of the one-step
+    // launches for such m, which the multi-step launches repeat exactly)
+    if (o.ordering == JEVD_ORD_MODMODULUS && n % 2 == 0 && n >= 4 && m > 512 &&
+        m <= kRingStepsMaxRows && (V == nullptr || defer_v) && nslots == n / 2) {
+        if (n % 4 == 0) ring_steps = 2;
+    }
+    if (ring_steps > 1) {
+        st = grow_device(&h->dgalt, &h->capGalt, (size_t)ldg * n);
+        if (st) return st;
+    }
+    h->info.steps_per_launch = ring_steps;
     int chunk = 0;
     if (defer_v) {
         const size_t fit = kVlogMaxBytes / ((size_t)nslots * sizeof(double2));
         chunk = (int)std::min<size_t>((size_t)nsteps, std::max<size_t>(1, fit));
         chunk = std::min(chunk, kVlogMaxSteps);
+        // runs of whole multi-step launches
+        chunk = std::max(ring_steps, chunk / ring_steps * ring_steps);
         st = grow_device(&h->dvlog, &h->capVlog, (size_t)2 * chunk * nslots);
         if (st) return st;
         if (!h->vstream) HIP_TRY(hipStreamCreateWithFlags(&h->vstream, hipStreamNonBlocking));
@@ -489,37 +514,47 @@ static int run_pointwise(jevd_handle_t h, int m, int n, double *G, int ldg, cons
         HIP_TRY(h->timer.begin(h->stream, JEVD_K_PAIR_STEP));
         int kc = 0, timed = 0;   // first step of the current run; launches in the group
         double2 *logb = nullptr;
-        for (int k = 0; k < nsteps; ++k) {
+        for (int k = 0; k < nsteps; k += ring_steps) {
             if (defer_v && k == kc) {
                 const int b = runs % 2;
                 if (pending[b]) HIP_TRY(hipStreamWaitEvent(h->stream, h->evApplied[b], 0));
                 logb = h->dvlog + (size_t)b * chunk * nslots;
             }
-            PairStepArgs a{G, m, (long)ldg, V, n, (long)ldv, h->dpairs + h->hstep[k],
-                           h->hstep[k + 1] - h->hstep[k], dJ, tol, h->dctr + s, pf,
-                           h->dslots, h->dslots + nslots,
-                           defer_v ? logb + (size_t)(k - kc) * nslots : nullptr};
-            HIP_TRY(launch_pair_step(a, h->stream));
+            double2 *logk = defer_v ? logb + (size_t)(k - kc) * nslots : nullptr;
+            if (ring_steps > 1) {
+                // launch l of the sweep reads the copy it wrote last
+                const bool even = (k / ring_steps) % 2 == 0;
+                RingStepsArgs ra{even ? G : h->dgalt, even ? h->dgalt : G, m, (long)ldg,
+                                 h->dpairs + h->hstep[k], nslots, ring_steps, dJ, tol,
+                                 h->dctr + s, h->dslots, h->dslots + nslots, logk, nslots};
+                HIP_TRY(launch_pair_steps_ring(ra, h->stream));
+            } else {
+                PairStepArgs a{G, m, (long)ldg, V, n, (long)ldv, h->dpairs + h->hstep[k],
+                               h->hstep[k + 1] - h->hstep[k], dJ, tol, h->dctr + s, pf,
+                               h->dslots, h->dslots + nslots, logk};
+                HIP_TRY(launch_pair_step(a, h->stream));
+            }
             ++timed;
-            if (defer_v && (k + 1 - kc == chunk || k + 1 == nsteps)) {
+            const int kn = k + ring_steps;   // the next launch's first step
+            if (defer_v && (kn - kc == chunk || kn == nsteps)) {
                 const int b = runs % 2;
                 HIP_TRY(h->timer.end(h->stream, timed));
                 timed = 0;
                 HIP_TRY(hipEventRecord(h->evLogged[b], h->stream));
                 HIP_TRY(hipStreamWaitEvent(h->vstream, h->evLogged[b], 0));
                 HIP_TRY(h->timer.begin(h->vstream, JEVD_K_UPDATE));
-                VlogApplyArgs va{V, n, n, (long)ldv, h->dpairs, h->dstep, kc, k + 1, logb,
+                VlogApplyArgs va{V, n, n, (long)ldv, h->dpairs, h->dstep, kc, kn, logb,
                                  nslots, h->maxPairsPerStep};
                 HIP_TRY(launch_apply_vlog(va, h->vstream));
                 HIP_TRY(h->timer.end(h->vstream, 1));
                 HIP_TRY(hipEventRecord(h->evApplied[b], h->vstream));
                 pending[b] = true;
                 ++runs;
-                kc = k + 1;
-                if (k + 1 < nsteps) HIP_TRY(h->timer.begin(h->stream, JEVD_K_PAIR_STEP));
+                kc = kn;
+                if (kn < nsteps) HIP_TRY(h->timer.begin(h->stream, JEVD_K_PAIR_STEP));
             }
         }
-        if (!defer_v) HIP_TRY(h->timer.end(h->stream, nsteps));
+        if (!defer_v) HIP_TRY(h->timer.end(h->stream, timed));
         HIP_TRY(launch_sum_slots(h->dslots, h->dslots + nslots, nslots, h->dctr + s, h->stream));
         HIP_TRY(hipMemcpyAsync(h->hctr + s, h->dctr + s, sizeof(SweepCounters), hipMemcpyDeviceToHost,
                                h->stream));

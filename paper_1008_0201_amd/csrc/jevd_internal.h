@@ -162,6 +162,27 @@ struct KernelTimer {
 };
 
 hipError_t launch_pair_step(const PairStepArgs &a, hipStream_t st);
+
+// `steps` (2) consecutive steps of the ring (modified modulus, even n,
+// m <= 1024) in one launch of p workgroups, bit for bit the steps of
+// launch_pair_step; G read from Gin, written to Gout.
+struct RingStepsArgs {
+    const double *Gin;
+    double *Gout;
+    int m;
+    long ldg;
+    const int2 *pairs;  // the table from the launch's first step on (p pairs per step)
+    int p;              // pairs per step (n / 2)
+    int steps;
+    const signed char *J;
+    double tol;
+    SweepCounters *ctr;
+    unsigned *slot_rot, *slot_clamp;
+    double2 *vlog;      // null, or the log row of the first step
+    int vlog_stride;    // entries between the log rows of consecutive steps
+};
+constexpr int kRingStepsMaxRows = 1024;
+hipError_t launch_pair_steps_ring(const RingStepsArgs &a, hipStream_t st);
 hipError_t launch_apply_vlog(const VlogApplyArgs &a, hipStream_t st);
 
 struct BatchInst;

@@ -711,6 +711,179 @@ __global__ __launch_bounds__(BS) void k_finalize(const double *__restrict__ G, i
     }
 }
 
+// S consecutive steps of the modified modulus ordering on even n (the ring
+// of Alg. 3.1) in one launch, for m <= 1024.  In the ring, process r takes
+// the column it receives at step k + 1 from process r + 1 (mod p) and keeps
+// the other.  Workgroup w owns process w and also runs processes w + 1 ..
+// w + S - 1 (their owners run them too, with the same arithmetic): at step
+// j of the launch group g (process w + g, 256 threads) is active while
+// g <= S - 1 - j, and hands the column it gives up to group g - 1 through
+// LDS.  Every group runs its pair as k_pair_step<256, 4> does (the same
+// loads, sums, block reduction, test, transform and rotation), so the
+// results are bit for bit those of one launch per step; the owner's group
+// alone writes the rotation log, the slot counters and, after the last
+// step, its two columns.  G is read from Gin and written to Gout (a second
+// buffer), since the other workgroups still read Gin.  pairs: the table of
+// step k (p pairs per step, by slot; slot b runs process slot_process(b)).
+constexpr int kRingGroupThreads = 256, kRingRows = 4;
+
+__device__ __forceinline__ int ring_slot_of(int r, int p)
+{
+    // the inverse of slot_process in ordering.cpp
+    if (p % 8) return r;
+    const int per = p / 8;
+    return (r % per) * 8 + r / per;
+}
+
+template <int S>
+__global__ __launch_bounds__(S *kRingGroupThreads) void k_pair_steps_ring(
+    const double *__restrict__ Gin, double *__restrict__ Gout, int m, long ldg,
+    const int2 *__restrict__ pairs, int p, const signed char *__restrict__ J, double tol,
+    SweepCounters *__restrict__ ctr, unsigned *__restrict__ slot_rot,
+    unsigned *__restrict__ slot_clamp, double2 *__restrict__ vlog, int vlog_stride)
+{
+    constexpr int BS = kRingGroupThreads, CH = kRingRows, NWG = BS / kWave;
+    __shared__ double sh[S][3 * NWG];
+    __shared__ double box[S][BS * CH];   // the column group g gives up, rows in order
+    __shared__ signed char js[BS * CH];  // J (n <= m <= 1024)
+    const int g = threadIdx.x / BS, t = threadIdx.x % BS, wv = t / kWave;
+    // workgroup b runs the process of slot b (the XCD that ran it in the
+    // one-step launches, whose L2 holds the columns it hands on)
+    const int owner = (p % 8) ? (int)blockIdx.x : (int)(blockIdx.x % 8) * (p / 8) + (int)blockIdx.x / 8;
+    const int proc = (owner + g) % p;
+    const int slot = ring_slot_of(proc, p);
+    // this process's pairs of the launch's steps, and J, read once
+    int2 pqs[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) pqs[j] = pairs[(size_t)j * p + slot];
+    if (J)
+        for (int e = threadIdx.x; e < 2 * p; e += S * BS) js[e] = J[e];
+    int ck = pqs[0].x, cn = pqs[0].y;   // K: kept from step to step, N: received
+    double K[CH], N[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int r = t + k * BS;
+        K[k] = (r < m) ? Gin[(size_t)ck * ldg + r] : 0.0;
+        N[k] = (r < m) ? Gin[(size_t)cn * ldg + r] : 0.0;
+    }
+    __syncthreads();   // js
+    for (int j = 0; j < S; ++j) {
+        const bool act = g <= S - 1 - j;
+        const bool kx = ck < cn;   // K holds the pair's first column
+        double app = 0.0, aqq = 0.0, apq = 0.0;
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const double xp = kx ? K[k] : N[k], xq = kx ? N[k] : K[k];
+                app = fma(xp, xp, app);
+                aqq = fma(xq, xq, aqq);
+                apq = fma(xp, xq, apq);
+            }
+        }
+        // block_sum3<256> within the group
+        app = wave_sum(app);
+        aqq = wave_sum(aqq);
+        apq = wave_sum(apq);
+        if ((t & (kWave - 1)) == 0) {
+            sh[g][wv] = app;
+            sh[g][NWG + wv] = aqq;
+            sh[g][2 * NWG + wv] = apq;
+        }
+        __syncthreads();
+        if (act) {
+            app = sh[g][0];
+            aqq = sh[g][NWG];
+            apq = sh[g][2 * NWG];
+#pragma unroll
+            for (int i = 1; i < NWG; ++i) {
+                app += sh[g][i];
+                aqq += sh[g][NWG + i];
+                apq += sh[g][2 * NWG + i];
+            }
+            const int pp = kx ? ck : cn, qq = kx ? cn : ck;
+            double2 entry = make_double2(1.0, 0.0);
+            if (!finite3(app, aqq, apq)) {
+                if (g == 0 && t == 0) ctr->nonfinite = 1u;
+            } else if (needs_rotation(app, aqq, apq, tol)) {
+                const bool same = (J == nullptr) || (js[pp] == js[qq]);
+                double c, sn;
+                const bool clamped = transform_params(app, aqq, apq, same, c, sn);
+                entry = log_entry(c, sn, same);
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    double xp = kx ? K[k] : N[k], xq = kx ? N[k] : K[k];
+                    rotate_elems(xp, xq, c, sn, same);
+                    K[k] = kx ? xp : xq;
+                    N[k] = kx ? xq : xp;
+                }
+                if (g == 0 && t == 0) {
+                    slot_rot[slot] += 1u;
+                    if (clamped) slot_clamp[slot] += 1u;
+                }
+            }
+            if (g == 0 && t == 0 && vlog) vlog[(size_t)j * vlog_stride + slot] = entry;
+        }
+        if (j + 1 == S) break;
+        // the next pair of this process: keep the shared column in K, give up
+        // the other (into the box, for group g - 1), receive from group g + 1
+        int cnext = -1;
+        if (act) {
+            int2 nx = pqs[0];
+#pragma unroll
+            for (int i = 1; i < S; ++i)
+                if (i == j + 1) nx = pqs[i];
+            if (ck != nx.x && ck != nx.y) {
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const double x = K[k];
+                    K[k] = N[k];
+                    N[k] = x;
+                }
+                const int x = ck;
+                ck = cn;
+                cn = x;
+            }
+            if (g > 0)
+#pragma unroll
+                for (int k = 0; k < CH; ++k) box[g][t + k * BS] = N[k];
+            cnext = (nx.x == ck) ? nx.y : nx.x;
+        }
+        __syncthreads();
+        if (g <= S - 2 - j) {
+            // group g + 1 gave up exactly this column (the ring hands it on)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) N[k] = box[g + 1][t + k * BS];
+            cn = cnext;
+        }
+        __syncthreads();   // the boxes are rewritten after the next step
+    }
+    if (g == 0) {
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int r = t + k * BS;
+            if (r < m) {
+                Gout[(size_t)ck * ldg + r] = K[k];
+                Gout[(size_t)cn * ldg + r] = N[k];
+            }
+        }
+    }
+}
+
+hipError_t launch_pair_steps_ring(const RingStepsArgs &a, hipStream_t st)
+{
+    if (a.m > kRingGroupThreads * kRingRows || a.p < 1) return hipErrorInvalidValue;
+    switch (a.steps) {
+    case 2:
+        k_pair_steps_ring<2><<<a.p, 2 * kRingGroupThreads, 0, st>>>(
+            a.Gin, a.Gout, a.m, a.ldg, a.pairs, a.p, a.J, a.tol, a.ctr, a.slot_rot, a.slot_clamp,
+            a.vlog, a.vlog_stride);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- launchers
 template <int BS, int CH>
 static void launch_ch(const PairStepArgs &a, hipStream_t st)

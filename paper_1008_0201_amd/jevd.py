@@ -42,7 +42,8 @@ class jevd_info(ctypes.Structure):
                 ("ordering", ctypes.c_int), ("rotations", ctypes.c_longlong * INFO_MAX_SWEEPS),
                 ("clamps", ctypes.c_longlong), ("breakdowns", ctypes.c_longlong),
                 ("kernel_ms", ctypes.c_double * 4), ("kernel_launches", ctypes.c_longlong * 4),
-                ("sweeps_low", ctypes.c_int), ("v_deferred", ctypes.c_int)]
+                ("sweeps_low", ctypes.c_int), ("v_deferred", ctypes.c_int),
+                ("steps_per_launch", ctypes.c_int)]
 
 
 class JevdError(RuntimeError):

@@ -115,6 +115,22 @@ def test_block_matches_pointwise_definition(solver, orc, variant):
     check_eigs(orc, wl.G, None, got["lam"], ref.lam)
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_block_literal_recipe_lam6(solver, orc, variant):
+    """The block workload's recipe taken literally (lam = 10^U(-6,0), so
+    kappa(Q diag(lam) Q^T) = 1e6) at n = 512, b = 64: the FP64 oracle itself
+    is not within 1e-12 of the exact eigenvalues there, so the gate fixed in
+    advance decides by its second test, the relative accuracy bound (1.2),
+    64 n u kappa_2(B), against the 80-bit oracle."""
+    wl = W.graded_spd_transposed(512, k=2, lam_decades=6.0)
+    got = run(solver, wl.G, None, wl.tol, variant, 64, want_V=False)
+    assert got["st"] == 0
+    ref = orc.block_jevd(wl.G, None, wl.tol, b=64, full_block=variant == 2, want_v=False,
+                         nthreads=0)
+    res = check_eigs(orc, wl.G, None, got["lam"], ref.lam)
+    print("n=512 literal recipe (lam 1e-6..1) variant %d: %s" % (variant, res))
+
+
 def test_block_workload_recipe_small(solver, orc):
     """The block workload's recipe at n = 1024 against the block oracle
     (same ordering, b = 32, block-oriented)."""

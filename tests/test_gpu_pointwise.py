@@ -154,9 +154,28 @@ def test_hyperbolic_graded_n1024_full_size(solver, orc):
     J = diag(+1 x 512, -1 x 512), modified modulus, tol = n eps."""
     wl = W.graded_hyperbolic(1024)
     got = run_gpu(solver, wl.G, wl.J, wl.tol, W.MODMODULUS)
+    # two steps of the ring per launch (n a multiple of 4, 512 < m <= 1024)
+    assert got["info"].steps_per_launch == 2 and got["info"].v_deferred == 1
     ref = check_against_oracle(orc, wl.G, wl.J, wl.tol, W.MODMODULUS, got)
     print("n=1024 hyperbolic sweeps gpu %d oracle %d, rel err %.3e" %
           (got["sweeps"], ref.sweeps, rel_err(got["lam"], ref.lam)))
+
+
+@pytest.mark.parametrize("m,n,want_V,spl", [(600, 520, True, 2), (1024, 516, False, 2),
+                                             (514, 514, True, 1), (512, 512, True, 1),
+                                             (1100, 520, True, 1), (700, 602, True, 1)])
+def test_ring_two_step_launches(solver, orc, m, n, want_V, spl):
+    """Two ring steps per launch where n is a multiple of 4 and 512 < m <=
+    1024 (each workgroup also runs the next process of the ring and hands
+    its column on through LDS; G alternates between two buffers), one step
+    per launch elsewhere; against the oracle either way."""
+    g = np.random.default_rng(m + 7 * n)
+    G = g.standard_normal((m, n)) * (10.0 ** g.uniform(-2, 2, size=n))[None, :]
+    J = np.ones(n, dtype=np.int8)
+    J[g.permutation(n)[: n // 3]] = -1
+    got = run_gpu(solver, G, J, n * EPS, W.MODMODULUS, want_V=want_V)
+    assert got["info"].steps_per_launch == spl
+    check_against_oracle(orc, G, J, n * EPS, W.MODMODULUS, got)
 
 
 def test_status_paths(solver, orc):
