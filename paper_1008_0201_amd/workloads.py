@@ -85,7 +85,10 @@ def graded_hyperbolic(n=1024, k=1, m=None, grade=3.0, ordering=MODMODULUS):
 # every machine produces the same bytes (eigenvalues of an input can then be
 # computed once, on any machine, and looked up by the input's SHA-256), that
 # recipe runs in a child process with both fixed: the AVX2 (Haswell) kernels,
-# which every x86-64 host here has, and 8 threads.
+# which every x86-64 host here has, and 8 threads.  OpenBLAS uses no more
+# threads than the CPUs the process may run on, so a process restricted to
+# fewer than 8 CPUs (an affinity mask) gets other bytes; it is warned, and
+# lookups of cached results by SHA-256 then report that the input differs.
 FIXED_BLAS_ENV = {"OPENBLAS_CORETYPE": "Haswell", "OPENBLAS_NUM_THREADS": "8",
                   "OMP_NUM_THREADS": "8"}
 
@@ -106,6 +109,11 @@ def _graded_spd_factor_fixed_blas(n, k, lam_decades, row_decades):
     import sys
     import tempfile
     here = os.path.dirname(os.path.abspath(__file__))
+    ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    if ncpu < int(FIXED_BLAS_ENV["OPENBLAS_NUM_THREADS"]):
+        print("workloads: only %d CPUs allowed; the generated factor will differ from the "
+              "one made with %s threads" % (ncpu, FIXED_BLAS_ENV["OPENBLAS_NUM_THREADS"]),
+              file=sys.stderr)
     env = dict(os.environ)
     env.update(FIXED_BLAS_ENV)
     with tempfile.TemporaryDirectory() as td:
