@@ -202,7 +202,8 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
  * (n <= 48, <= 96, <= 141, larger), each run with workgroups of 4, 8 or 16
  * wavefronts (4, 2 or 1 instances at a time per CU, with that share of its
  * LDS): the size jevd_batch_autotune measured fastest for the class on this
- * machine when the class's per-step arrays fit that share, else 16.
+ * machine when the class's per-step arrays fit that share and the class has
+ * more instances than the device has CUs, else 16.
  * Consecutive classes of one size share a persistent launch (largest
  * instances first); the largest class's launch runs on `stream`, the others
  * at the same time on a second stream of the plan.
@@ -216,7 +217,9 @@ int jacobi_evd(jevd_handle_t h, int m, int n, double *G, int ldg, const signed c
  * the per-instance sweep counts and statuses (JEVD_OK, JEVD_ENOCONV,
  * JEVD_ENONFINITE); either array may be NULL.  It returns JEVD_OK if every
  * instance converged, else the first failing instance's status.
- * Plans of one handle may not run concurrently.
+ * Plans of one handle may not run concurrently, and are destroyed before
+ * the handle.  A destroyed plan's device arrays are kept by the handle for
+ * the next plan (no allocation when they are large enough).
  */
 typedef struct jevd_batch_s *jevd_batch_t;
 

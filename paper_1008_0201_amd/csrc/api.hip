@@ -56,6 +56,8 @@ struct jevd_batch_s {
     int *d_sweeps = nullptr;   // per instance
     int *d_status = nullptr;   // per instance
     signed char *d_J = nullptr;
+    void *arena = nullptr;   // one device allocation holding the arrays above
+    size_t arena_bytes = 0;
     hipStream_t last = nullptr;
     bool ran = false;
 };
@@ -108,6 +110,10 @@ struct jevd_handle_s {
     size_t capVlog = 0;
     double *dgalt = nullptr;     // second copy of G for the multi-step ring launches
     size_t capGalt = 0;
+    // device arena of the last destroyed batch plan, reused by the next one
+    // (a fresh hipMalloc can take tens of milliseconds)
+    void *batch_pool = nullptr;
+    size_t batch_pool_bytes = 0;
     hipStream_t vstream = nullptr;   // second stream of the deferred V update
     hipEvent_t evLogged[2] = {nullptr, nullptr};    // a log buffer is complete
     hipEvent_t evApplied[2] = {nullptr, nullptr};   // V is updated from a log buffer
@@ -331,6 +337,7 @@ int jevd_destroy(jevd_handle_t h)
     if (h->dslots) (void)hipFree(h->dslots);
     if (h->dvlog) (void)hipFree(h->dvlog);
     if (h->dgalt) (void)hipFree(h->dgalt);
+    if (h->batch_pool) (void)hipFree(h->batch_pool);
     if (h->vstream) {
         (void)hipStreamSynchronize(h->vstream);
         (void)hipStreamDestroy(h->vstream);
@@ -791,12 +798,16 @@ int jevd_batch_destroy(jevd_batch_t p)
 {
     if (!p) return JEVD_OK;
     if (p->ran) (void)hipStreamSynchronize(p->last);
-    if (p->d_inst) (void)hipFree(p->d_inst);
-    if (p->d_order) (void)hipFree(p->d_order);
-    if (p->d_queue) (void)hipFree(p->d_queue);
-    if (p->d_sweeps) (void)hipFree(p->d_sweeps);
-    if (p->d_status) (void)hipFree(p->d_status);
-    if (p->d_J) (void)hipFree(p->d_J);
+    if (p->arena) {
+        // kept by the handle for the next plan (the larger of the two)
+        if (p->arena_bytes > p->h->batch_pool_bytes) {
+            if (p->h->batch_pool) (void)hipFree(p->h->batch_pool);
+            p->h->batch_pool = p->arena;
+            p->h->batch_pool_bytes = p->arena_bytes;
+        } else {
+            (void)hipFree(p->arena);
+        }
+    }
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->aux) (void)hipStreamDestroy(p->aux);
@@ -857,12 +868,29 @@ int jevd_batch_create(jevd_handle_t h, int batch, const int *m, const int *n, do
         return e == hipErrorOutOfMemory ? JEVD_ENOMEM : JEVD_EHIP;
     };
     hipError_t e;
-    if ((e = hipMalloc((void **)&p->d_inst, sizeof(BatchInst) * batch)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc((void **)&p->d_order, sizeof(int) * batch)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc((void **)&p->d_queue, sizeof(int) * kBatchClasses)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc((void **)&p->d_sweeps, sizeof(int) * batch)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc((void **)&p->d_status, sizeof(int) * batch)) != hipSuccess) return fail(e);
-    if ((e = hipMalloc((void **)&p->d_J, hJ.size())) != hipSuccess) return fail(e);
+    // one arena for the plan's arrays, 256-byte aligned pieces; the handle's
+    // kept arena when it is large enough
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_order = up(sizeof(BatchInst) * batch), o_queue = o_order + up(sizeof(int) * batch),
+                 o_sweeps = o_queue + up(sizeof(int) * kBatchClasses),
+                 o_status = o_sweeps + up(sizeof(int) * batch), o_J = o_status + up(sizeof(int) * batch),
+                 total = o_J + up(hJ.size() + 1);
+    if (h->batch_pool && h->batch_pool_bytes >= total) {
+        p->arena = h->batch_pool;
+        p->arena_bytes = h->batch_pool_bytes;
+        h->batch_pool = nullptr;
+        h->batch_pool_bytes = 0;
+    } else {
+        if ((e = hipMalloc(&p->arena, total)) != hipSuccess) return fail(e);
+        p->arena_bytes = total;
+    }
+    char *base = (char *)p->arena;
+    p->d_inst = (BatchInst *)base;
+    p->d_order = (int *)(base + o_order);
+    p->d_queue = (int *)(base + o_queue);
+    p->d_sweeps = (int *)(base + o_sweeps);
+    p->d_status = (int *)(base + o_status);
+    p->d_J = (signed char *)(base + o_J);
     for (int i = 0; i < batch; ++i) {
         BatchInst &d = hi[i];
         d.G = G[i];
@@ -899,7 +927,10 @@ int jevd_batch_create(jevd_handle_t h, int batch, const int *m, const int *n, do
         off += p->cls_cnt[c];
         if (p->cls_cnt[c] == 0) continue;
         const int tw = tuned_batch_waves(c);
-        const int w = (tw > 0 && batch_waves_fit(tw, nmax[c])) ? tw : default_batch_waves(c);
+        int w = (tw > 0 && batch_waves_fit(tw, nmax[c])) ? tw : default_batch_waves(c);
+        // the tuner times batches of several instances per CU; with at most
+        // one per CU a smaller workgroup would leave the rest of the CU idle
+        if (p->cls_cnt[c] <= cus) w = 16;
         p->cls_waves[c] = batch_waves_fit(w, nmax[c]) ? w : 16;
         if (p->ngrp > 0 && p->grp_waves[p->ngrp - 1] == p->cls_waves[c]) {
             p->grp_cnt[p->ngrp - 1] += p->cls_cnt[c];

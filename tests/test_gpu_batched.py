@@ -174,6 +174,12 @@ def test_batched_plan_rerun_and_graph_replay(solver, split, tmp_path):
     import torch
     from paper_1008_0201_amd import jevd
     items = mixed_batch()[4:14]
+    if split:
+        # classes 0 and 1 with more instances than CUs (so they keep the
+        # table's 4 and 8 wavefronts)
+        g = np.random.default_rng(77)
+        for n in [int(x) for x in g.integers(8, 41, size=300)] + [int(x) for x in g.integers(49, 91, size=300)]:
+            items.append((g.standard_normal((n, n)), None, n * EPS, n))
     G0 = [dev_colmajor(G) for (G, J, tol, ld) in items]
     Gd = [x.clone() for x in G0]
     if split:
@@ -231,9 +237,9 @@ def test_batched_plan_rerun_and_graph_replay(solver, split, tmp_path):
 @pytest.mark.parametrize("waves", [(4, 4, 4, 4), (8, 8, 8, 8), (16, 16, 16, 16), (4, 8, 16, 16),
                                    (16, 8, 4, 16)])
 def test_batched_every_workgroup_size_matches_oracle(solver, orc, waves, tmp_path):
-    """The tune table's per-class workgroup sizes (class 0 .. 3): every size
-    the kernel is built for, alone or mixed over the classes (then one to
-    four launches on two streams), gives the oracle's results."""
+    """The tune table's per-class workgroup sizes (class 0 .. 3) on a batch
+    of 20 instances: classes with no more instances than CUs run 16
+    wavefronts whatever the table says, and give the oracle's results."""
     from paper_1008_0201_amd import jevd
     path = str(tmp_path / "tune.txt")
     try:
@@ -247,8 +253,9 @@ def test_batched_every_workgroup_size_matches_oracle(solver, orc, waves, tmp_pat
             got = jevd.jevd_batch_waves(plan.plan)
         finally:
             plan.close()
-        # every class's step arrays (n <= 300 here) fit the smallest LDS share
-        assert got == list(waves), got
+        # a class with no more instances than CUs runs 16 wavefronts (one
+        # instance per CU); this batch has 20 instances
+        assert got == [16, 16, 16, 16], got
         res = run_batch(solver, items, W.MODMODULUS)
     finally:
         jevd.jevd_tune_file(None)
@@ -270,3 +277,45 @@ def test_batched_autotune_records_a_size_per_class(solver, tmp_path):
         assert "batch 0 " in open(path).read()
     finally:
         jevd.jevd_tune_file(None)
+
+
+@pytest.mark.parametrize("waves", [4, 8])
+def test_batched_small_workgroups_on_large_classes(solver, orc, waves, tmp_path):
+    """Classes with more instances than CUs run the table's workgroup size:
+    300 instances of class 1 (49 <= n <= 96, G and V in LDS) and 300 of
+    class 3 (n > 141: G in HBM, the register step and the V log) with 4 or 8
+    wavefronts per workgroup.  Every instance: U orthonormal and, J = I,
+    sum(lambda) = ||G||_F^2 (orthogonal transforms keep the Frobenius norm);
+    six instances per class against the oracle."""
+    import torch
+    from paper_1008_0201_amd import jevd
+    g = np.random.default_rng(4242 + waves)
+    ns = [int(x) for x in g.integers(49, 97, size=300)] + [int(x) for x in g.integers(142, 181, size=300)]
+    Gs = [g.standard_normal((n, n)) * (10.0 ** g.uniform(-1.5, 1.5, size=n))[None, :] for n in ns]
+    items = [(G, None, G.shape[1] * EPS, G.shape[0]) for G in Gs]
+    path = str(tmp_path / "tune.txt")
+    try:
+        assert jevd.jevd_tune_file(path) == jevd.JEVD_OK
+        for c in range(jevd.BATCH_CLASSES):
+            assert jevd.jevd_batch_tune_record(c, waves, 1.0) == jevd.JEVD_OK
+        plan = solver.batch_plan([dev_colmajor(G) for G in Gs], None, None)
+        try:
+            got = jevd.jevd_batch_waves(plan.plan)
+        finally:
+            plan.close()
+        assert got == [0, waves, 0, waves], got
+        res = run_batch(solver, items, W.MODMODULUS)
+    finally:
+        jevd.jevd_tune_file(None)
+    for i, (G, r) in enumerate(zip(Gs, res)):
+        n = G.shape[1]
+        assert r["st"] == 0, (i, r["st"])
+        U = r["U"]
+        assert np.max(np.abs(U.T @ U - np.eye(n))) <= 10 * n * EPS, i
+        fro = float(np.sum(G.astype(np.longdouble) ** 2))
+        assert abs(float(np.sum(r["lam"].astype(np.longdouble))) - fro) <= 10 * n * EPS * fro, i
+    for i in list(range(6)) + list(range(300, 306)):
+        G = Gs[i]
+        check_instance(orc, G, None, G.shape[1] * EPS, W.MODMODULUS, res[i]["lam"], res[i]["U"],
+                       res[i]["V"], res[i]["G"], res[i]["sweeps"], res[i]["st"],
+                       "waves %d instance %d n=%d" % (waves, i, G.shape[1]))
