@@ -114,6 +114,8 @@ struct jevd_handle_s {
     // (a fresh hipMalloc can take tens of milliseconds)
     void *batch_pool = nullptr;
     size_t batch_pool_bytes = 0;
+    void *batch_stage = nullptr;   // pinned host image of a plan's arena (one copy)
+    size_t batch_stage_bytes = 0;
     hipStream_t vstream = nullptr;   // second stream of the deferred V update
     hipEvent_t evLogged[2] = {nullptr, nullptr};    // a log buffer is complete
     hipEvent_t evApplied[2] = {nullptr, nullptr};   // V is updated from a log buffer
@@ -338,6 +340,7 @@ int jevd_destroy(jevd_handle_t h)
     if (h->dvlog) (void)hipFree(h->dvlog);
     if (h->dgalt) (void)hipFree(h->dgalt);
     if (h->batch_pool) (void)hipFree(h->batch_pool);
+    if (h->batch_stage) (void)hipHostFree(h->batch_stage);
     if (h->vstream) {
         (void)hipStreamSynchronize(h->vstream);
         (void)hipStreamDestroy(h->vstream);
@@ -950,11 +953,23 @@ int jevd_batch_create(jevd_handle_t h, int batch, const int *m, const int *n, do
         if ((e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming)) != hipSuccess)
             return fail(e);
     }
-    if ((e = hipMemcpy(p->d_inst, hi.data(), sizeof(BatchInst) * batch, hipMemcpyHostToDevice)) != hipSuccess)
-        return fail(e);
-    if ((e = hipMemcpy(p->d_order, order.data(), sizeof(int) * batch, hipMemcpyHostToDevice)) != hipSuccess)
-        return fail(e);
-    if ((e = hipMemcpy(p->d_J, hJ.data(), hJ.size(), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+    // the instance table, the order and the signs in one copy from a pinned
+    // image of the arena (copies from pageable memory have stalled for tens
+    // of milliseconds)
+    const size_t used = o_J + hJ.size();
+    if (h->batch_stage_bytes < used) {
+        if (h->batch_stage) (void)hipHostFree(h->batch_stage);
+        h->batch_stage = nullptr;
+        h->batch_stage_bytes = 0;
+        if ((e = hipHostMalloc(&h->batch_stage, used, hipHostMallocDefault)) != hipSuccess) return fail(e);
+        h->batch_stage_bytes = used;
+    }
+    char *img = (char *)h->batch_stage;
+    std::memset(img, 0, used);
+    std::memcpy(img, hi.data(), sizeof(BatchInst) * batch);
+    std::memcpy(img + o_order, order.data(), sizeof(int) * batch);
+    if (!hJ.empty()) std::memcpy(img + o_J, hJ.data(), hJ.size());
+    if ((e = hipMemcpy(p->arena, img, used, hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
     *plan = p;
     return JEVD_OK;
 }
