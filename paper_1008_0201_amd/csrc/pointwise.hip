@@ -601,18 +601,11 @@ __global__ __launch_bounds__(NW *kWave) void k_rowcyclic_solve(
                 const int e = 4 * wave + grp;
                 const bool active = e < np;
                 const int p = active ? p0 + e : p0, q = t - p;   // a valid pair when idle
-                double x[kRcRows], y[kRcRows], vx[kRcRows], vy[kRcRows];
+                double x[kRcRows], y[kRcRows];
 #pragma unroll
                 for (int i = 0; i < kRcRows; ++i) {
                     x[i] = g[p * P + 16 * i + l16];
                     y[i] = g[q * P + 16 * i + l16];
-                }
-                if (V) {
-#pragma unroll
-                    for (int i = 0; i < kRcRows; ++i) {
-                        vx[i] = v[p * P + 16 * i + l16];
-                        vy[i] = v[q * P + 16 * i + l16];
-                    }
                 }
                 double app = 0.0, aqq = 0.0, apq = 0.0;
 #pragma unroll
@@ -636,11 +629,13 @@ __global__ __launch_bounds__(NW *kWave) void k_rowcyclic_solve(
                         g[q * P + 16 * i + l16] = y[i];
                     }
                     if (V) {
+                        // V is read only for a pair that rotates
 #pragma unroll
                         for (int i = 0; i < kRcRows; ++i) {
-                            rotate_elems(vx[i], vy[i], c, sn, same);
-                            v[p * P + 16 * i + l16] = vx[i];
-                            v[q * P + 16 * i + l16] = vy[i];
+                            double vx = v[p * P + 16 * i + l16], vy = v[q * P + 16 * i + l16];
+                            rotate_elems(vx, vy, c, sn, same);
+                            v[p * P + 16 * i + l16] = vx;
+                            v[q * P + 16 * i + l16] = vy;
                         }
                     }
                     if (l16 == 0) {
