@@ -331,7 +331,7 @@ def run_batched(args):
             sweep_diff = max(sweep_diff, abs(ref.sweeps - sw[i]))
             if e > 1e-12:
                 # the FP64 oracle itself misses 1e-12 on ill-conditioned
-                # instances: judge both against the 80-bit oracle, with the
+                # instances: gate both against the 80-bit oracle, with the
                 # FP64 error scale taken from two oracle runs that differ in
                 # their rounding sequence (two orderings)
                 hi = O.jevd(wls[i].G, wls[i].J, wls[i].tol, W.MODMODULUS, want_v=False, prec="l")
