@@ -42,7 +42,9 @@ Workloads (seeded, synthetic; paper_1008_0201_amd/workloads.py):
       P_i (12 m_i + 6 n_i)
   adjoint-256x128: 256 indefinite instances of n = m = 128 (the batch
       recipe's indefinite kind), loss L = sum_i w_i lambda_i + <C, U> with
-      w, C ~ N(0,1); a step is the differentiated solve: batched forward,
+      w, C ~ N(0,1); a step is the differentiated solve: batched forward
+      (the solve on the batch plan the front end keeps for this shape and
+      signature set, whose creation the first warm-up step pays),
       canonical form, and the adjoint (jevd_adjoint); work = forward sweep
       work + 8 m n^2 per instance for the four adjoint contractions
 """
@@ -517,7 +519,8 @@ def run_adjoint(args):
         "data": "synthetic (seeded)",
         "config": {"workload": "adjoint-256x128", "instances": count, "m": m, "n": n,
                    "J": "random +-1 (30-70 % negative)", "ordering": "modified modulus",
-                   "step": "forward (batched solve + canonical form) + backward (adjoint)",
+                   "step": "forward (batched solve on the cached plan + canonical form) + "
+                           "backward (adjoint)",
                    "sweeps_range": [min(sw), max(sw)], "input_generation_s": round(t_gen, 1)},
         "adjoint_ms": round(adj_ms, 4),
         "roofline": roofline,

@@ -227,6 +227,37 @@ def test_autograd_matches_oracle_solve_and_finite_differences(torch_dev, orc, m,
         assert np.all(np.abs(fd - an) <= 1e-7 * scale), (fd, an)
 
 
+def test_autograd_plan_cache_reuse(torch_dev):
+    """The forward reuses a batch plan (and its workspace) for a repeated
+    shape, signature set and tolerance: results of cached plans, including
+    one re-created after eviction, equal those of fresh plans bit for bit."""
+    torch = torch_dev
+    from paper_1008_0201_amd import autograd as AG
+    G1, J1, _, _ = recipe(4, 60, 48, 31)
+    G2, J2, _, _ = recipe(4, 60, 48, 32)
+    Gs, Js, _, _ = recipe(3, 30, 20, 33)
+
+    def fresh(G, J):
+        AG._release()
+        return gpu_forward(torch, G, J)
+
+    cases = [(G1, J1), (G2, J2), (G2, J1), (Gs, Js)]
+    refs = [fresh(G, J) for G, J in cases]
+    AG._release()
+    # hits (same key, other G), misses (other J, other shape), and evictions
+    # (more keys than the cache holds) before the first key comes back
+    seq = [0, 1, 0, 2, 3, 1]
+    extra = [recipe(2, 24 + 2 * i, 16 + i, 40 + i) for i in range(AG._PLAN_CACHE_MAX)]
+    for i in seq:
+        lam, U = gpu_forward(torch, *cases[i])
+        assert np.array_equal(lam, refs[i][0]) and np.array_equal(U, refs[i][1]), i
+    for G, J, _, _ in extra:
+        gpu_forward(torch, G, J)
+    assert len(AG._plans) == AG._PLAN_CACHE_MAX
+    lam, U = gpu_forward(torch, *cases[0])
+    assert np.array_equal(lam, refs[0][0]) and np.array_equal(U, refs[0][1])
+
+
 def test_adjoint_invalid_arguments(torch_dev):
     from paper_1008_0201_amd import jevd as B
     s = B.Solver()
