@@ -57,11 +57,16 @@ struct InstCtx {
     // per vsteps steps instead of once per step
     int vsteps;            // 0: V is rotated at once
     double *vlog;          // LDS: vsteps x (n/2 + 1) x (c, s)
-    int *vflag;            // LDS: vsteps x (n/2 + 1) transform types
+    int *vflag;            // LDS: vsteps x (n/2 + 1) log_entry words (0: no transform)
     double *vrows;         // LDS: NW * kVRows rows of V, n each
 };
 
 constexpr int kVRows = 2;   // rows of V per wavefront in the deferred apply
+
+// A logged transform's word: its type (1 trigonometric, 2 hyperbolic) and
+// its columns p < q (n <= 4096), so that applying the log to the rows of V
+// reads the pair instead of recomputing it for every row.
+__device__ __forceinline__ int log_entry(int type, int p, int q) { return type | (p << 2) | (q << 17); }
 
 // LDS bytes kept beside G and V: the signs and the per-pair step arrays.
 // Rounded to 16 bytes so that the arrays at the top of LDS stay aligned.
@@ -252,7 +257,7 @@ __device__ __forceinline__ void two_pairs(double *g, long ldg, double *v, long l
         if (logfl && lane == 0) {
             logcs[2 * ee[k]] = cs;
             logcs[2 * ee[k] + 1] = sn;
-            logfl[ee[k]] = same ? 1 : 2;
+            logfl[ee[k]] = log_entry(same ? 1 : 2, pp[k], qq[k]);
         }
         double *gp = g + (size_t)pp[k] * ldg, *gq = g + (size_t)qq[k] * ldg;
 #pragma unroll
@@ -280,6 +285,93 @@ __device__ __forceinline__ void two_pairs(double *g, long ldg, double *v, long l
     }
 }
 
+// two_pairs without V (V logged or absent), with the scalar part of the two
+// pairs in one pass: lane k (k = lane & 1) runs the threshold test and the
+// transform of pair k, and lanes 0 and 1 hand the results to the wavefront.
+// The step is bound by VALU issue, and the transform is most of a pair's
+// instructions, so two pairs share one pass instead of running one each.
+// Each lane runs the per-pair expressions of two_pairs on the same sums
+// (transform_params_bf gives transform_params' values), so the results are
+// the same to the bit.
+template <int R>
+__device__ __forceinline__ void two_pairs_nov(double *g, long ldg, const InstCtx &c, int p0, int q0,
+                                              bool has1, int p1, int q1, int lane, unsigned &rot,
+                                              int &bad, double *logcs, int *logfl, int e0, int e1)
+{
+    const int pp[2] = {p0, p1}, qq[2] = {q0, q1};
+    double a[2][R], b[2][R];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !has1) break;
+        const double *gp = g + (size_t)pp[k] * ldg, *gq = g + (size_t)qq[k] * ldg;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = lane + 64 * i;
+            a[k][i] = r < c.m ? gp[r] : 0.0;
+            b[k][i] = r < c.m ? gq[r] : 0.0;
+        }
+    }
+    double app[2] = {0.0, 0.0}, aqq[2] = {0.0, 0.0}, apq[2] = {0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !has1) break;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            app[k] = fma(a[k][i], a[k][i], app[k]);
+            aqq[k] = fma(b[k][i], b[k][i], aqq[k]);
+            apq[k] = fma(a[k][i], b[k][i], apq[k]);
+        }
+        app[k] = wave_sum(app[k]);
+        aqq[k] = wave_sum(aqq[k]);
+        apq[k] = wave_sum(apq[k]);
+    }
+    const bool odd = (lane & 1) != 0;
+    const double sp = odd ? app[1] : app[0], sq = odd ? aqq[1] : aqq[0], spq = odd ? apq[1] : apq[0];
+    const bool same = odd ? c.J[p1] == c.J[q1] : c.J[p0] == c.J[q0];
+    const bool fin = finite3(sp, sq, spq);
+    int f = 0;
+    double cs = 0.0, sn = 0.0;
+    if ((!odd || has1) && fin && needs_rotation(sp, sq, spq, c.tol)) {
+        transform_params_bf(sp, sq, spq, same, cs, sn);
+        f = same ? 1 : 2;
+    }
+    const int fk[2] = {__builtin_amdgcn_readlane(f, 0), __builtin_amdgcn_readlane(f, 1)};
+    const int nonfin = __builtin_amdgcn_readlane((int)!fin, 0) | (has1 ? __builtin_amdgcn_readlane((int)!fin, 1) : 0);
+    if (nonfin) bad = 1;
+    const double ck[2] = {read_lane(cs, 0), read_lane(cs, 1)}, sk[2] = {read_lane(sn, 0), read_lane(sn, 1)};
+    if (logfl && lane == 0) {   // every logged pair gets an entry (0: no transform)
+        logfl[e0] = fk[0] ? log_entry(fk[0], p0, q0) : 0;
+        if (fk[0]) {
+            logcs[2 * e0] = ck[0];
+            logcs[2 * e0 + 1] = sk[0];
+        }
+        if (has1) {
+            logfl[e1] = fk[1] ? log_entry(fk[1], p1, q1) : 0;
+            if (fk[1]) {
+                logcs[2 * e1] = ck[1];
+                logcs[2 * e1 + 1] = sk[1];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        if (k == 1 && !has1) break;
+        if (!fk[k]) continue;
+        const bool sm = fk[k] == 1;
+        double *gp = g + (size_t)pp[k] * ldg, *gq = g + (size_t)qq[k] * ldg;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            const int r = lane + 64 * i;
+            rotate_elems(a[k][i], b[k][i], ck[k], sk[k], sm);
+            if (r < c.m) {
+                gp[r] = a[k][i];
+                gq[r] = b[k][i];
+            }
+        }
+        if (lane == 0) ++rot;
+    }
+}
+
 // One step over G in global memory by the register path (R > 0; two pairs
 // per wavefront for R <= 2, one for R = 4, registers permitting).
 template <int NW, int R>
@@ -289,7 +381,15 @@ __device__ __forceinline__ void global_step(double *g, long ldg, double *v, long
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int np = modulus_step_pairs(c.n, k, modified);
-    if constexpr (R <= 2) {
+    if (!v) {
+        for (int e = wave; e < np; e += 2 * NW) {
+            int p0, q0, p1 = 0, q1 = 0;
+            modulus_pair(c.n, k, e, &p0, &q0);
+            const bool has1 = e + NW < np;
+            if (has1) modulus_pair(c.n, k, e + NW, &p1, &q1);
+            two_pairs_nov<R>(g, ldg, c, p0, q0, has1, p1, q1, lane, rot, bad, logcs, logfl, e, e + NW);
+        }
+    } else if constexpr (R <= 2) {
         for (int e = wave; e < np; e += 2 * NW) {
             int p0, q0, p1 = 0, q1 = 0;
             modulus_pair(c.n, k, e, &p0, &q0);
@@ -311,8 +411,11 @@ __device__ __forceinline__ void global_step(double *g, long ldg, double *v, long
 // Applies the logged transforms of steps kfirst .. kfirst + nsteps - 1 to V
 // (HBM, column-major): blocks of NW * kVRows rows are staged in LDS;
 // a wavefront owns kVRows rows and runs every logged step on them, lanes over
-// the step's pairs.  A row's elements are rotated in the same order as by
-// immediate application, so V is the same to the bit.
+// the step's pairs, each log entry (pair, type, c, s) read once for its rows.
+// A row's elements meet the same transforms in the same order as by
+// immediate application; each element's rotation is c x -+ s y with the
+// products fused as the compiler chooses at this site, so V can differ from
+// immediate application in the last bit of an element.
 template <int NW>
 __device__ __forceinline__ void apply_v_log(double *v, long ldv, const InstCtx &c, int kfirst,
                                             int nsteps, bool modified)
@@ -327,22 +430,32 @@ __device__ __forceinline__ void apply_v_log(double *v, long ldv, const InstCtx &
             if (i < nr) c.vrows[i * n + col] = v[(size_t)col * ldv + r0 + i];
         }
         __syncthreads();
-        for (int ii = 0; ii < kVRows; ++ii) {
-            const int i = wave * kVRows + ii;
-            if (i >= nr) break;
-            double *row = c.vrows + (size_t)i * n;
+        // both rows of the wavefront in one pass over the log, each logged
+        // entry read once for the two
+        static_assert(kVRows == 2, "the pass below takes two rows");
+        const int i0 = wave * kVRows;
+        if (i0 < nr) {
+            double *row0 = c.vrows + (size_t)i0 * n, *row1 = row0 + n;
+            const bool has1 = i0 + 1 < nr;
             for (int st = 0; st < nsteps; ++st) {
-                const int k = kfirst + st;
-                const int np = modulus_step_pairs(n, k, modified);
+                const int np = modulus_step_pairs(n, kfirst + st, modified);
                 for (int e = lane; e < np; e += 64) {
                     const int f = c.vflag[st * lp + e];
                     if (f == 0) continue;
-                    int p, q;
-                    modulus_pair(n, k, e, &p, &q);
-                    double x = row[p], y = row[q];
-                    rotate_elems(x, y, c.vlog[2 * (st * lp + e)], c.vlog[2 * (st * lp + e) + 1], f == 1);
-                    row[p] = x;
-                    row[q] = y;
+                    const int p = (f >> 2) & 0x7fff, q = f >> 17;
+                    const double cs = c.vlog[2 * (st * lp + e)], sn = c.vlog[2 * (st * lp + e) + 1];
+                    const bool same = (f & 3) == 1;
+                    double x = row0[p], y = row0[q];
+                    rotate_elems(x, y, cs, sn, same);
+                    row0[p] = x;
+                    row0[q] = y;
+                    if (has1) {
+                        x = row1[p];
+                        y = row1[q];
+                        rotate_elems(x, y, cs, sn, same);
+                        row1[p] = x;
+                        row1[q] = y;
+                    }
                 }
                 // the next step's pairs read columns other lanes wrote: the
                 // LDS accesses of one wavefront complete in order, and the
