@@ -46,8 +46,8 @@ class _Plan:
     (column-major instances, ld = m) and the solver's lam, U and V, which the
     forward canonicalises into fresh tensors.  A plan may be run again
     (jevd_batch_run restarts the queue and sets V to I), and the forwards
-    that share it run on one stream, so the workspace is free again once
-    the next forward's copy into it is enqueued."""
+    that share it run in order on one stream, so a forward's copy into the
+    workspace runs after the previous forward's last read of it."""
 
     def __init__(self, s, nb, m, n, Jh, tol, max_sweeps, device):
         self.Gw = torch.empty((nb, n, m), dtype=torch.float64, device=device)
