@@ -9,8 +9,50 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // FP64 operands (the addend and the signs optional),
 // op(A) M x K, op(B) K x N.  A 64 x 64 tile of D per workgroup of four
 // wavefronts (2 x 2, each 32 x 32 as 2 x 2 MFMA tiles of 16 x 16); K in
-// chunks of 16 staged through LDS.  Tails in M, N, K are zero-filled.
-constexpr int kTile = 64, kKc = 16, kPitch = kTile + 1;
+// chunks of 32 staged through LDS, the next chunk loaded into registers
+// while the MFMAs run on the current one.  Tails in M, N, K are
+// zero-filled.  The MFMAs accumulate over k in increasing order whatever
+// the chunking.
+constexpr int kTile = 64, kKc = 32, kPitch = kTile + 1;
+constexpr int kPer = kKc * kTile / 256;   // elements of each operand per thread and chunk
+
+// Thread tid's share of a chunk: op(A)[i][k] and op(B)[kb][j], with
+// consecutive threads on consecutive addresses of the column-major operands.
+template <bool TA, bool TB>
+__device__ __forceinline__ void chunk_index(int tid, int r, int &i, int &k, int &j, int &kb)
+{
+    if (!TA) {   // op(A)[i][k] = A[i + k lda]
+        i = tid & 63;
+        k = (tid >> 6) + 4 * r;
+    } else {     // op(A)[i][k] = A[k + i lda]
+        k = tid & 31;
+        i = (tid >> 5) + 8 * r;
+    }
+    if (!TB) {   // op(B)[k][j] = B[k + j ldb]
+        kb = tid & 31;
+        j = (tid >> 5) + 8 * r;
+    } else {     // op(B)[k][j] = B[j + k ldb]
+        j = tid & 63;
+        kb = (tid >> 6) + 4 * r;
+    }
+}
+
+template <bool TA, bool TB>
+__device__ __forceinline__ void load_chunk(const GemmArgs &g, const double *A, const double *B, int i0,
+                                           int j0, int k0, int tid, double (&xa)[kPer],
+                                           double (&xb)[kPer])
+{
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        int i, k, j, kb;
+        chunk_index<TA, TB>(tid, r, i, k, j, kb);
+        const int gi = i0 + i, gk = k0 + k, gj = j0 + j, gkb = k0 + kb;
+        xa[r] = (gi < g.M && gk < g.K) ? (TA ? A[gk + (size_t)gi * g.lda] : A[gi + (size_t)gk * g.lda])
+                                       : 0.0;
+        xb[r] = (gj < g.N && gkb < g.K) ? (TB ? B[gj + (size_t)gkb * g.ldb] : B[gkb + (size_t)gj * g.ldb])
+                                        : 0.0;
+    }
+}
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_bgemm(GemmArgs g)
@@ -29,35 +71,19 @@ __global__ __launch_bounds__(256) void k_bgemm(GemmArgs g)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
 
+    double xa[kPer], xb[kPer];
+    load_chunk<TA, TB>(g, A, B, i0, j0, 0, tid, xa, xb);
     for (int k0 = 0; k0 < g.K; k0 += kKc) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int i, k;
-            if (!TA) {   // op(A)[i][k] = A[i + k lda]: consecutive threads, consecutive i
-                i = tid & 63;
-                k = (tid >> 6) + 4 * r;
-            } else {     // op(A)[i][k] = A[k + i lda]: consecutive threads, consecutive k
-                k = tid & 15;
-                i = (tid >> 4) + 16 * r;
-            }
-            const int gi = i0 + i, gk = k0 + k;
-            double x = 0.0;
-            if (gi < g.M && gk < g.K) x = TA ? A[gk + (size_t)gi * g.lda] : A[gi + (size_t)gk * g.lda];
-            As[k][i] = x;
-            int j, kb;
-            if (!TB) {   // op(B)[k][j] = B[k + j ldb]
-                kb = tid & 15;
-                j = (tid >> 4) + 16 * r;
-            } else {     // op(B)[k][j] = B[j + k ldb]
-                j = tid & 63;
-                kb = (tid >> 6) + 4 * r;
-            }
-            const int gj = j0 + j, gkb = k0 + kb;
-            double y = 0.0;
-            if (gj < g.N && gkb < g.K) y = TB ? B[gj + (size_t)gkb * g.ldb] : B[gkb + (size_t)gj * g.ldb];
-            Bs[kb][j] = y;
+        for (int r = 0; r < kPer; ++r) {
+            int i, k, j, kb;
+            chunk_index<TA, TB>(tid, r, i, k, j, kb);
+            As[k][i] = xa[r];
+            Bs[kb][j] = xb[r];
         }
         __syncthreads();
+        // the next chunk's loads are in flight during this chunk's MFMAs
+        if (k0 + kKc < g.K) load_chunk<TA, TB>(g, A, B, i0, j0, k0 + kKc, tid, xa, xb);
 #pragma unroll
         for (int kk = 0; kk < kKc; kk += 4) {
             const int kr = kk + lane / 16;
