@@ -75,27 +75,48 @@ __global__ __launch_bounds__(64) void k_canonical(
 }
 
 // ------------------------------------------------------------- middle step
-// M'_ki from K (n x n, null for C = 0), lambda and w (null for w = 0).
+// M'_ki from K (n x n, null for C = 0), lambda and w (null for w = 0).  A
+// 32 x 32 tile of M' per workgroup: the matching tiles of K and of K^T are
+// read with consecutive threads on consecutive rows and staged in LDS, so
+// neither read is strided.
+constexpr int kMidTile = 32;
 __global__ __launch_bounds__(256) void k_adj_mid(int m, int n, const double *__restrict__ lam,
                                                  long long slam, const double *__restrict__ w,
                                                  long long sw, const double *__restrict__ K,
                                                  double *__restrict__ Mp)
 {
-    const int b = blockIdx.y;
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long long)n * n) return;
-    const int k = (int)(e % n), i = (int)(e / n);
-    const double *lb = lam + b * slam;
-    const double li = lb[i];
+    __shared__ double t1[kMidTile][kMidTile + 1];   // t1[c][r] = K[k0 + r, i0 + c]
+    __shared__ double t2[kMidTile][kMidTile + 1];   // t2[c][r] = K[i0 + r, k0 + c]
+    const int b = blockIdx.z;
+    const int k0 = blockIdx.x * kMidTile, i0 = blockIdx.y * kMidTile;
+    const int tx = threadIdx.x % kMidTile, ty = threadIdx.x / kMidTile;
+    constexpr int kRowsPerPass = 256 / kMidTile;
     const double *Kb = K ? K + (size_t)b * n * n : nullptr;
-    double v;
-    if (k == i) {
-        v = w ? 2.0 * w[b * sw + i] : 0.0;
-    } else {
-        v = Kb ? (Kb[k + (size_t)i * n] - Kb[i + (size_t)k * n]) / (li - lb[k]) : 0.0;
+    if (Kb) {
+        for (int c = ty; c < kMidTile; c += kRowsPerPass) {
+            const int i = i0 + c, k = k0 + tx;
+            t1[c][tx] = (i < n && k < n) ? Kb[k + (size_t)i * n] : 0.0;
+            const int kc = k0 + c, ir = i0 + tx;
+            t2[c][tx] = (kc < n && ir < n) ? Kb[ir + (size_t)kc * n] : 0.0;
+        }
     }
-    if (Kb && m > n) v -= Kb[k + (size_t)i * n] / li;
-    Mp[(size_t)b * n * n + e] = v;
+    __syncthreads();
+    const double *lb = lam + b * slam;
+    for (int c = ty; c < kMidTile; c += kRowsPerPass) {
+        const int i = i0 + c, k = k0 + tx;
+        if (i >= n || k >= n) continue;
+        const double li = lb[i];
+        const double kki = Kb ? t1[c][tx] : 0.0;   // K[k, i]
+        const double kik = Kb ? t2[tx][c] : 0.0;   // K[i, k]
+        double v;
+        if (k == i) {
+            v = w ? 2.0 * w[b * sw + i] : 0.0;
+        } else {
+            v = Kb ? (kki - kik) / (li - lb[k]) : 0.0;
+        }
+        if (Kb && m > n) v -= kki / li;
+        Mp[(size_t)b * n * n + k + (size_t)i * n] = v;
+    }
 }
 
 // ------------------------------------------------------------------- host
@@ -133,7 +154,8 @@ hipError_t launch_adjoint(int batch, int m, int n, const double *G, int ldg, lon
         launch_gemm(true, false, g, batch, st);
     }
     {
-        dim3 grid((unsigned)((nn + 255) / 256), batch);
+        const unsigned tiles = (unsigned)((n + kMidTile - 1) / kMidTile);
+        dim3 grid(tiles, tiles, batch);
         k_adj_mid<<<grid, 256, 0, st>>>(m, n, lam, slam, w, sw, C ? wsK : nullptr, wsM);
     }
     {   // T = U M' [+ C Lambda^{-1} when m > n]
